@@ -1,0 +1,297 @@
+/*
+ * gsopt.h -- C ABI of the MI355X (gfx950) AdamW-GS optimizer step.
+ *
+ * Method: "A Step to Decouple Optimization in 3DGS" (ICLR 2026, arXiv
+ * 2601.16736).  AdamW-GS recouples three parts (Sec. "Recoupling: AdamW-GS"):
+ *   - Sparse Adam: only primitives visible from the current view advance
+ *     their moments, step count and attributes (Sec. "Characteristics of
+ *     Sparse Adam", sparse-beta equation), each with its own step count t_i
+ *     (asynchronous indexing, Sec. "Update-step decoupling");
+ *   - Re-State Regularization (RSR): at scheduled iterations a uniform sample
+ *     of the existing primitives has its moments rescaled, m <- alpha1 m,
+ *     v <- alpha2 v (Re-State equation);
+ *   - Decoupled Attribute Regularization (DAR): the moments see only the
+ *     photometric gradient (decoupled-moment equation) and the regulariser
+ *     enters the update outside them, preconditioned by sqrt(v_hat) and
+ *     clamped at C (DAR update equation; per-attribute forms for opacity and
+ *     log-scale in Sec. "Implementation Details / AdamW-GS").
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller; the library
+ *     never frees them and keeps no reference after the call is enqueued.
+ *     Structs passed by pointer (gs_camera, gs_group, gs_step_config,
+ *     gs_scene) are HOST memory, read during the call only.
+ *   - Every call is asynchronous on `stream` (0 = the null stream).
+ *   - Argument errors are found on the host before anything is enqueued and
+ *     return GS_EINVAL; nothing is launched then.  A failed launch returns
+ *     GS_EHIP.  gs_last_error() gives the calling thread's last message.
+ *   - NaN and Inf propagate per element; nothing is clamped or "repaired".
+ *   - Indices are int32: n must be below 2^31.
+ *   - Attribute groups are row-major [n][dim] (the 3DGS convention of one
+ *     tensor per attribute group).  Rows of one group are updated
+ *     independently, so groups may be views into one packed buffer as long
+ *     as no two groups overlap.
+ */
+#ifndef GSOPT_H
+#define GSOPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSOPT_VERSION 1
+#define GS_MAX_GROUPS 8
+
+typedef enum {
+    GS_OK = 0,
+    GS_EINVAL = 1,        /* invalid argument; nothing enqueued */
+    GS_EHIP = 2,          /* a HIP call or kernel launch failed */
+    GS_ENOMEM = 3,        /* allocation failed (plans and the tuner only) */
+    GS_EUNSUPPORTED = 4   /* valid but not supported here (e.g. no gfx950 device) */
+} gs_status;
+
+/* Last error message of the calling thread ("" if none).  Never NULL. */
+const char* gs_last_error(void);
+
+/* GSOPT_VERSION of the built library. */
+int32_t gs_version(void);
+
+/* ------------------------------------------------------------------------
+ * Visibility (the filter V of the sparse-beta equation).
+ *
+ * The paper takes V from the rasterizer ("visible from the current
+ * viewpoint").  Here V is the frustum/radius cull of each projected mean,
+ * defined as an FP32 computation in this exact order, one rounding per
+ * operation and no fused multiply-add, so that a reimplementation anywhere
+ * reproduces the mask bit for bit:
+ *   p = R mu + t           each row as ((R_k0*x + R_k1*y) + R_k2*z) + t_k
+ *   visible requires  z_near < p_z < z_far
+ *   u = (fx*p_x)/p_z + cx,   v = (fy*p_y)/p_z + cy
+ *   r = (max(fx,fy)*rho_i)/p_z and r >= r_min_px   if radius != NULL, else r = 0
+ *   u + r >= 0,  u - r <= width,  v + r >= 0,  v - r <= height
+ * A NaN anywhere makes the primitive invisible.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float view[12];          /* row-major 3x4 [R|t], world -> camera; camera looks along +z,
+                                image x right, y down */
+    float fx, fy, cx, cy;    /* pixels */
+    int32_t width, height;   /* pixels, >= 1 */
+    float z_near, z_far;     /* 0 <= z_near < z_far; z_far may be +INFINITY */
+    float r_min_px;          /* radius cull threshold; used only when radius != NULL */
+} gs_camera;
+
+/*
+ * means   [n][3] FP32, 4-byte aligned.
+ * radius  [n] FP32 world-space bounding radius per primitive, or NULL.
+ * mask    [n] uint8 out (1 visible, 0 not), or NULL.
+ * vis_idx [n] int32 out: indices of the visible primitives, or NULL.  The
+ *         order is unspecified (rows are updated independently, so it does
+ *         not change any result); each visible index appears exactly once.
+ * vis_count  device int32 scalar out (number of visible primitives); required
+ *         when vis_idx != NULL.  It is overwritten, not accumulated.
+ * At least one of mask and vis_idx must be non-NULL.
+ */
+gs_status gs_visibility(const float* means, const float* radius, int64_t n,
+                        const gs_camera* cam, uint8_t* mask, int32_t* vis_idx,
+                        int32_t* vis_count, hipStream_t stream);
+
+/*
+ * Compaction alone: vis_idx/vis_count from an existing mask ([n] uint8,
+ * nonzero = visible).  Same output contract as gs_visibility.
+ */
+gs_status gs_compact(const uint8_t* mask, int64_t n, int32_t* vis_idx, int32_t* vis_count,
+                     hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The step.
+ * ---------------------------------------------------------------------- */
+typedef enum {
+    GS_DAR_NONE = 0,               /* plain sparse Adam ("other attributes" equation) */
+    GS_DAR_OPACITY_SIGMOID = 1,    /* theta = opacity logit tau, R'(tau) = sigma(tau)(1 - sigma(tau)) */
+    GS_DAR_LOGSCALE_EXP = 2        /* theta = log-scale kappa,  R'(kappa) = exp(kappa) */
+} gs_dar_kind;
+
+typedef enum {
+    GS_REG_ADAPTIVE = 0,           /* DAR: + min(lambda R'/N_I' / (sqrt(v_hat)+eps), C)   (AdamW-GS) */
+    GS_REG_CONSTANT = 1,           /* AdamW-style constant penalty: + lambda R'            (comparison variant) */
+    GS_REG_CONSTANT_CLIPPED = 2    /* AdamW-style, clipped: + min(lambda R', C)            (comparison variant) */
+} gs_reg_mode;
+
+typedef enum { GS_MOMENT_F32 = 0, GS_MOMENT_BF16 = 1 } gs_moment_dtype;
+
+typedef enum {
+    GS_SCHED_AUTO = 0,       /* the tuner's choice for (n, visible_hint, dtype), else by inputs */
+    GS_SCHED_COMPACTED = 1,  /* waves take slices of vis_idx (needs vis_idx, vis_count) */
+    GS_SCHED_MASKED = 2,     /* waves sweep windows of the mask (needs visible) */
+    GS_SCHED_DENSE = 3       /* V = 1 for all n primitives: synchronous Adam + DAR */
+} gs_schedule;
+
+typedef struct {
+    float* param;            /* theta [n][dim] FP32, updated in place */
+    const float* grad;       /* photometric gradient [n][dim] FP32; read on visible rows only */
+    void* exp_avg;           /* m [n][dim], FP32 or BF16 per moment_dtype, updated in place */
+    void* exp_avg_sq;        /* v [n][dim], same dtype as exp_avg */
+    int32_t dim;             /* >= 1 */
+    int32_t dar_kind;        /* gs_dar_kind */
+    int32_t reg_mode;        /* gs_reg_mode (ignored when dar_kind == GS_DAR_NONE) */
+    int32_t reserved;        /* must be 0 */
+    double lr;               /* eta of this attribute group, finite */
+    double dar_lambda;       /* lambda_theta >= 0 */
+    double dar_clip;         /* C >= 0 (the paper's C_t, a constant per group) */
+} gs_group;
+
+typedef struct {
+    double beta1, beta2;     /* 0 <= beta < 1 */
+    double eps;              /* > 0, added outside the square root */
+    double reg_norm;         /* N_I' > 0: pixel normaliser of DAR; see gs_reg_norm() */
+    uint64_t seed;           /* key of the RSR sampler and the stochastic-rounding draws */
+    int64_t iteration;       /* training iteration; keys the draws together with seed */
+    int32_t moment_dtype;    /* gs_moment_dtype */
+    int32_t stochastic_round;/* BF16 only: 1 = stochastic rounding of moment writes, 0 = nearest-even */
+    int32_t rsr_enable;      /* 1 = apply Re-State Regularization in this call */
+    int32_t schedule;        /* gs_schedule */
+    double rsr_alpha1;       /* 0 <= alpha1 < 1 */
+    double rsr_alpha2;       /* 0 <= alpha2 < 1 (the paper uses alpha2 = alpha1^2) */
+    double rsr_ratio;        /* sampling probability p in [0, 1] */
+    float visible_hint;      /* expected visible fraction for GS_SCHED_AUTO (<= 0: unknown) */
+    int32_t unit;            /* rows (compacted) / primitives (masked, dense) per wave; 0 = default */
+} gs_step_config;
+
+/*
+ * N_I' from the image pixel count N_I: the most significant decimal digit
+ * of N_I is kept and the result divided by ten (DAR paragraph of Sec.
+ * "Hyperparameter Selection"); e.g. 1000*1000 -> 1e5.  Returns 0 for N_I < 1.
+ */
+double gs_reg_norm(double n_pixels);
+
+/*
+ * One AdamW-GS step over the groups of one scene (Sec. "Recoupling:
+ * AdamW-GS"; equations referenced at the top of this file).
+ *
+ * For every primitive i, in this order:
+ *  1. if rsr_enable and i is sampled (below), m <- alpha1 m and v <- alpha2 v
+ *     on every element of every group, visible or not; t_i is unchanged;
+ *  2. if i is not visible nothing else changes (theta, m, v, t_i);
+ *  3. t_i <- t_i + 1, b1 = 1 - beta1^t_i, b2 = 1 - beta2^t_i;
+ *  4. per element: m <- beta1 m + (1-beta1) g;  v <- beta2 v + (1-beta2) g^2;
+ *     d = sqrt(v/b2) + eps;  u = (m/b1)/d;
+ *     DAR groups add min(lambda R'(theta)/N_I'/d, C) (or the reg_mode
+ *     variant), with R' at the pre-update theta;
+ *     theta <- theta - lr u.
+ * Sampling: the k-th output of a SplitMix64 stream with state s is
+ * mix64(s + k*0x9E3779B97F4A7C15) (Steele, Lea & Flood 2014).  With
+ * s1 = output (1+1) of the stream seeded with `seed` (tag 1) and
+ * s2 = output (iteration+1) of the stream with state s1, primitive i is
+ * sampled iff (output (i+1) of the stream with state s2) >> 32 is below
+ * floor(rsr_ratio * 2^32) (2^32 when rsr_ratio = 1).
+ * BF16 moments are computed in FP32 and rounded on store, to nearest-even or
+ * stochastically with 16 bits of a draw of tag 16+g (group g) keyed by the
+ * element index row*dim+col (m: bits 63..48, v: bits 47..32).
+ *
+ * visible     [n] uint8 mask (nonzero = visible), or NULL;
+ * vis_idx     [n] int32 visible indices (any order, no duplicates), or NULL;
+ * vis_count   device int32 scalar, length of vis_idx, or NULL;
+ * step_count  [n] int32 t_i, updated in place.
+ * GS_SCHED_MASKED needs `visible`; GS_SCHED_COMPACTED needs vis_idx and
+ * vis_count, and the index list must match the mask's visible set when both
+ * are given; GS_SCHED_DENSE ignores all three.  Pointers: 4-byte aligned
+ * (BF16 moments 2-byte); wider alignment lets rows use 64/128-bit accesses.
+ * Distinct groups must not overlap; overlapping arrays give undefined results.
+ */
+gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n,
+                        const uint8_t* visible, const int32_t* vis_idx, const int32_t* vis_count,
+                        int32_t* step_count, const gs_step_config* cfg, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Many scenes in one persistent launch.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const gs_group* groups;  /* host array of n_groups descriptors (device arrays inside) */
+    int32_t n_groups;
+    int32_t schedule;        /* GS_SCHED_* for this scene (AUTO: tuner by visible_hint) */
+    int64_t n;
+    const uint8_t* visible;  /* as in adamw_gs_step */
+    const int32_t* vis_idx;
+    const int32_t* vis_count;
+    int32_t* step_count;
+    float visible_hint;      /* expected visible fraction (AUTO only) */
+    int32_t reserved;        /* must be 0 */
+} gs_scene;
+
+typedef struct gs_batch gs_batch;
+
+/*
+ * Builds a plan for n_scenes scenes: validates them, picks each scene's
+ * schedule, uploads the scene table to device memory and prepares a HIP
+ * graph holding the one persistent launch.  Allocates (device table, work
+ * queue counters); the step calls below do not.  The arrays the scenes
+ * point to must stay alive and in place while the plan is used.
+ */
+gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, gs_batch** out);
+
+/*
+ * One AdamW-GS step for every scene of the plan, as if adamw_gs_step were
+ * called once per scene s with cfg->seed + s as the seed (so the scenes'
+ * RSR samples and rounding draws are independent).  cfg->schedule and
+ * cfg->unit are ignored (the plan fixed them).  Replays the plan's graph
+ * (first call on a plan instantiates it); calls on one plan must not
+ * overlap in time (they share the plan's work-queue counters).
+ */
+gs_status adamw_gs_step_batched(gs_batch* batch, const gs_step_config* cfg, hipStream_t stream);
+
+/* Schedule chosen for scene s of the plan (GS_SCHED_*), or -1. */
+int32_t gs_batch_scene_schedule(const gs_batch* batch, int32_t s);
+
+/* Frees the plan (synchronizes with its last launch first). NULL is a no-op. */
+gs_status gs_batch_destroy(gs_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Relocation state reset (Sec. "Hyperparameter Selection", scaling in RSR:
+ * a reallocated primitive starts from zero optimizer state, i.e. RSR with
+ * alpha1 = alpha2 = 0).
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace gs_relocate_reset needs for n primitives. */
+size_t gs_relocate_workspace_size(int64_t n);
+
+/*
+ * Selects the k primitives with the smallest key (e.g. the opacity logit),
+ * ties broken by the lower index, and zeroes their m and v in every group;
+ * with reset_t also their step count.  key [n] FP32 device (finite values),
+ * 0 <= k <= n.  selected [k] int32 out (ascending indices) or NULL.
+ * workspace: device memory of gs_relocate_workspace_size(n) bytes, 256-byte
+ * aligned; contents on entry are ignored.
+ */
+gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_group* groups,
+                            int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
+                            int32_t reset_t, int32_t* selected, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Schedule tuner.
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Times the schedules (compacted, masked) and their wave-unit sizes on
+ * synthetic buffers of n primitives with the given group dims, at the given
+ * visible fraction and moment dtype, and records the fastest for
+ * GS_SCHED_AUTO.  Allocates and frees its own buffers; synchronizes the
+ * device.  Entries are kept per (log2 n, visible-fraction bucket, dtype).
+ * best_schedule / best_unit (host, may be NULL) receive the winner.
+ */
+gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, float visible_fraction,
+                  int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit);
+
+/* Removes every tuner entry. */
+void gs_tune_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSOPT_H */

@@ -80,12 +80,16 @@ def lib():
         L.orc_draw.restype = u64; L.orc_draw.argtypes = [u64, u64, i64, u64]
         L.orc_rsr_threshold.restype = u64; L.orc_rsr_threshold.argtypes = [ctypes.c_double]
         L.orc_rsr_sampled.restype = ctypes.c_int; L.orc_rsr_sampled.argtypes = [u64, i64, i64, ctypes.c_double]
+        L.orc_rsr_sample_mask.restype = None
+        L.orc_rsr_sample_mask.argtypes = [u64, i64, vp, i64, ctypes.c_double, vp]
         L.orc_reg_norm.restype = ctypes.c_double; L.orc_reg_norm.argtypes = [ctypes.c_double]
         L.orc_visible_f32.restype = ctypes.c_int; L.orc_visible_f32.argtypes = [vp, vp, vp]
         L.orc_visibility.restype = None; L.orc_visibility.argtypes = [vp, vp, i64, vp, vp]
         L.orc_visibility_f64.restype = None; L.orc_visibility_f64.argtypes = [vp, vp, i64, vp, vp]
         L.orc_compact.restype = i64; L.orc_compact.argtypes = [vp, i64, vp]
         L.orc_adamw_gs_step.restype = None; L.orc_adamw_gs_step.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.orc_adamw_gs_step_rows.restype = None
+        L.orc_adamw_gs_step_rows.argtypes = [vp, i32, i64, vp, vp, vp, vp]
         L.orc_select_smallest.restype = None; L.orc_select_smallest.argtypes = [vp, i64, i64, vp]
         L.orc_reset_state.restype = None; L.orc_reset_state.argtypes = [vp, i32, vp, i64, vp, i32]
         L.orc_bf16_rne.restype = ctypes.c_uint16; L.orc_bf16_rne.argtypes = [ctypes.c_float]
@@ -129,6 +133,17 @@ def rsr_threshold(ratio: float) -> int:
 
 def rsr_sampled(seed: int, iteration: int, i: int, ratio: float) -> bool:
     return bool(lib().orc_rsr_sampled(seed & (2**64 - 1), iteration, i, float(ratio)))
+
+
+def rsr_sample_mask(seed: int, iteration: int, n: int, ratio: float,
+                    ids: Optional[np.ndarray] = None) -> np.ndarray:
+    """Re-State sample flags (bool) of primitives 0..n-1, or of ``ids``."""
+    if ids is not None:
+        ids = _need(np.ascontiguousarray(ids), np.int64)
+        n = ids.shape[0]
+    out = np.zeros(n, np.uint8)
+    lib().orc_rsr_sample_mask(seed & (2**64 - 1), iteration, _ptr(ids), n, float(ratio), _ptr(out))
+    return out.astype(bool)
 
 
 def reg_norm(n_pixels: float) -> float:
@@ -256,20 +271,26 @@ def _config_struct(cfg: Config) -> _Config:
 
 
 def adamw_gs_step(groups: List[Group], n: int, visible: Optional[np.ndarray], t: np.ndarray,
-                  cfg: Config) -> None:
+                  cfg: Config, ids: Optional[np.ndarray] = None) -> None:
     """One AdamW-GS step (Sec. "Recoupling: AdamW-GS"; Eqs. of the sparse
     beta, Re-State, decoupled moments and DAR update), in place.
-    ``visible=None`` is V = 1 everywhere (synchronous Adam)."""
+    ``visible=None`` is V = 1 everywhere (synchronous Adam).  ``ids`` (int64,
+    optional) gives each row's primitive index in its scene when the rows are
+    a subset; it keys the Re-State draw."""
     _need(t, np.int32)
     if visible is not None:
         _need(visible, np.uint8)
+    if ids is not None:
+        _need(ids, np.int64)
+        if ids.shape[0] != n:
+            raise ValueError("ids must have n entries")
     for g in groups:
         if g.param.shape[0] != n:
             raise ValueError("group row count differs from n")
     arr = _groups_struct(groups)
     c = _config_struct(cfg)
-    lib().orc_adamw_gs_step(ctypes.addressof(arr), len(groups), n, _ptr(visible), _ptr(t),
-                            ctypes.addressof(c))
+    lib().orc_adamw_gs_step_rows(ctypes.addressof(arr), len(groups), n, _ptr(ids), _ptr(visible), _ptr(t),
+                                 ctypes.addressof(c))
 
 
 def select_smallest(key: np.ndarray, k: int) -> np.ndarray:

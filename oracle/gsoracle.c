@@ -83,6 +83,14 @@ int orc_rsr_sampled(uint64_t seed, int64_t iteration, int64_t i, double ratio)
     return u < orc_rsr_threshold(ratio);
 }
 
+/* Sample flags of n primitives (ids[k], or k when ids is NULL). */
+void orc_rsr_sample_mask(uint64_t seed, int64_t iteration, const int64_t* ids, int64_t n,
+                         double ratio, uint8_t* out)
+{
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = (uint8_t)orc_rsr_sampled(seed, iteration, ids ? ids[k] : k, ratio);
+}
+
 /* ------------------------------------------------------------------------ */
 /* DAR pixel-count normaliser (Sec. "Hyperparameter Selection", DAR          */
 /* paragraph): keep only the most significant decimal digit of N_I, then     */
@@ -249,16 +257,21 @@ static double reg_grad(int kind, double theta)
  *       u += min(lambda * R'(theta) / N_I' / d, C)   (groups with DAR)
  *       theta <- theta - lr * u
  *     R' is taken at the pre-update theta; d is this step's denominator.
+ * The rows may be a subset of a scene: ids[i] (NULL: i) is row i's index in
+ * the scene, which keys its Re-State draw.
  */
-void orc_adamw_gs_step(const orc_group* groups, int32_t n_groups, int64_t n,
-                       const uint8_t* visible, int32_t* t, const orc_config* cfg)
+void orc_adamw_gs_step_rows(const orc_group* groups, int32_t n_groups, int64_t n,
+                            const int64_t* ids, const uint8_t* visible, int32_t* t,
+                            const orc_config* cfg)
 {
     uint64_t thr = cfg->rsr_enable ? orc_rsr_threshold(cfg->rsr_ratio) : 0;
     uint64_t rsr_state = orc_stream_state(cfg->seed, ORC_TAG_RSR, cfg->iteration);
 
     for (int64_t i = 0; i < n; ++i) {
         if (cfg->rsr_enable) {
-            uint64_t u32 = orc_splitmix_output(rsr_state, (uint64_t)i + 1) >> 32;
+            /* the sample is keyed by the primitive's index in its scene */
+            uint64_t id = ids ? (uint64_t)ids[i] : (uint64_t)i;
+            uint64_t u32 = orc_splitmix_output(rsr_state, id + 1) >> 32;
             if (u32 < thr) {
                 for (int g = 0; g < n_groups; ++g) {
                     const orc_group* G = &groups[g];
@@ -305,6 +318,13 @@ void orc_adamw_gs_step(const orc_group* groups, int32_t n_groups, int64_t n,
             }
         }
     }
+}
+
+/* All n primitives of a scene: row i is primitive i. */
+void orc_adamw_gs_step(const orc_group* groups, int32_t n_groups, int64_t n,
+                       const uint8_t* visible, int32_t* t, const orc_config* cfg)
+{
+    orc_adamw_gs_step_rows(groups, n_groups, n, NULL, visible, t, cfg);
 }
 
 /* ------------------------------------------------------------------------ */

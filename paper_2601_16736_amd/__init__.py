@@ -1,0 +1,353 @@
+"""Python binding of libgsopt, the gfx950 AdamW-GS optimizer-step library.
+
+Argument marshalling only: every step of the path runs in the HIP kernels
+of ``libgsopt.so`` (built from ``csrc/`` by ``build.py``).  The names and
+arguments mirror the C ABI in ``include/gsopt.h``; tensors are passed as
+device pointers and streams as HIP stream handles.  There is no fallback:
+if the library is not built, importing this package raises.
+
+Method: "A Step to Decouple Optimization in 3DGS" (arXiv 2601.16736),
+Sec. "Recoupling: AdamW-GS" and Sec. "Implementation Details / AdamW-GS".
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsopt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2601_16736_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+GS_OK, GS_EINVAL, GS_EHIP, GS_ENOMEM, GS_EUNSUPPORTED = 0, 1, 2, 3, 4
+GS_DAR_NONE, GS_DAR_OPACITY_SIGMOID, GS_DAR_LOGSCALE_EXP = 0, 1, 2
+GS_REG_ADAPTIVE, GS_REG_CONSTANT, GS_REG_CONSTANT_CLIPPED = 0, 1, 2
+GS_MOMENT_F32, GS_MOMENT_BF16 = 0, 1
+GS_SCHED_AUTO, GS_SCHED_COMPACTED, GS_SCHED_MASKED, GS_SCHED_DENSE = 0, 1, 2, 3
+GS_MAX_GROUPS = 8
+
+_STATUS = {0: "GS_OK", 1: "GS_EINVAL", 2: "GS_EHIP", 3: "GS_ENOMEM", 4: "GS_EUNSUPPORTED"}
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gs_camera(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("z_near", ctypes.c_float), ("z_far", ctypes.c_float),
+                ("r_min_px", ctypes.c_float)]
+
+
+class gs_group(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p),
+                ("exp_avg_sq", ctypes.c_void_p), ("dim", ctypes.c_int32), ("dar_kind", ctypes.c_int32),
+                ("reg_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("dar_lambda", ctypes.c_double), ("dar_clip", ctypes.c_double)]
+
+
+class gs_step_config(ctypes.Structure):
+    _fields_ = [("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("reg_norm", ctypes.c_double), ("seed", ctypes.c_uint64), ("iteration", ctypes.c_int64),
+                ("moment_dtype", ctypes.c_int32), ("stochastic_round", ctypes.c_int32),
+                ("rsr_enable", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("rsr_alpha1", ctypes.c_double), ("rsr_alpha2", ctypes.c_double),
+                ("rsr_ratio", ctypes.c_double), ("visible_hint", ctypes.c_float), ("unit", ctypes.c_int32)]
+
+
+class gs_scene(ctypes.Structure):
+    _fields_ = [("groups", ctypes.POINTER(gs_group)), ("n_groups", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("n", ctypes.c_int64), ("visible", ctypes.c_void_p),
+                ("vis_idx", ctypes.c_void_p), ("vis_count", ctypes.c_void_p),
+                ("step_count", ctypes.c_void_p), ("visible_hint", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
+_i32, _i64, _u64, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
+_lib.gs_last_error.restype = ctypes.c_char_p
+_lib.gs_last_error.argtypes = []
+_lib.gs_version.restype = _i32
+_lib.gs_reg_norm.restype = ctypes.c_double
+_lib.gs_reg_norm.argtypes = [ctypes.c_double]
+_lib.gs_visibility.restype = _i32
+_lib.gs_visibility.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
+_lib.gs_compact.restype = _i32
+_lib.gs_compact.argtypes = [_vp, _i64, _vp, _vp, _vp]
+_lib.adamw_gs_step.restype = _i32
+_lib.adamw_gs_step.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, _vp, _vp,
+                               ctypes.POINTER(gs_step_config), _vp]
+_lib.gs_batch_create.restype = _i32
+_lib.gs_batch_create.argtypes = [ctypes.POINTER(gs_scene), _i32, ctypes.POINTER(_vp)]
+_lib.adamw_gs_step_batched.restype = _i32
+_lib.adamw_gs_step_batched.argtypes = [_vp, ctypes.POINTER(gs_step_config), _vp]
+_lib.gs_batch_scene_schedule.restype = _i32
+_lib.gs_batch_scene_schedule.argtypes = [_vp, _i32]
+_lib.gs_batch_destroy.restype = _i32
+_lib.gs_batch_destroy.argtypes = [_vp]
+_lib.gs_relocate_workspace_size.restype = _sz
+_lib.gs_relocate_workspace_size.argtypes = [_i64]
+_lib.gs_relocate_reset.restype = _i32
+_lib.gs_relocate_reset.argtypes = [_vp, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp, _vp,
+                                   _sz, _vp]
+_lib.gs_tune.restype = _i32
+_lib.gs_tune.argtypes = [_i64, ctypes.POINTER(_i32), _i32, ctypes.c_float, _i32, ctypes.POINTER(_i32),
+                         ctypes.POINTER(_i32)]
+_lib.gs_tune_clear.restype = None
+_lib.gs_tune_clear.argtypes = []
+
+EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_compact", "adamw_gs_step",
+            "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
+            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear"]
+
+
+def _check(status: int) -> None:
+    if status != GS_OK:
+        raise GsError(status, _lib.gs_last_error().decode())
+
+
+def _ptr(x) -> Optional[int]:
+    """Device pointer of a tensor (or an int address, or None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def last_error() -> str:
+    return _lib.gs_last_error().decode()
+
+
+def version() -> int:
+    return int(_lib.gs_version())
+
+
+def gs_reg_norm(n_pixels: float) -> float:
+    """N_I' (DAR paragraph of Sec. "Hyperparameter Selection")."""
+    return float(_lib.gs_reg_norm(float(n_pixels)))
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Camera:
+    view: Sequence[float]      # 12 floats, row-major 3x4 [R|t] world -> camera
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    z_near: float = 0.2
+    z_far: float = math.inf
+    r_min_px: float = 0.0
+
+    def to_c(self) -> gs_camera:
+        c = gs_camera()
+        flat = [float(v) for v in (self.view.reshape(-1) if hasattr(self.view, "reshape") else self.view)]
+        if len(flat) != 12:
+            raise ValueError("camera view must hold 12 values")
+        for k, v in enumerate(flat):
+            c.view[k] = v
+        c.fx, c.fy, c.cx, c.cy = float(self.fx), float(self.fy), float(self.cx), float(self.cy)
+        c.width, c.height = int(self.width), int(self.height)
+        c.z_near, c.z_far, c.r_min_px = float(self.z_near), float(self.z_far), float(self.r_min_px)
+        return c
+
+
+def gs_visibility(means, cam: Camera, mask=None, vis_idx=None, vis_count=None, radius=None, stream=None) -> None:
+    n = int(means.shape[0])
+    c = cam.to_c()
+    _check(_lib.gs_visibility(_ptr(means), _ptr(radius), n, ctypes.byref(c), _ptr(mask), _ptr(vis_idx),
+                              _ptr(vis_count), _stream(stream)))
+
+
+def gs_compact(mask, vis_idx, vis_count, stream=None) -> None:
+    _check(_lib.gs_compact(_ptr(mask), int(mask.shape[0]), _ptr(vis_idx), _ptr(vis_count), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Group:
+    param: object              # [n, dim] float32 device tensor
+    grad: object
+    exp_avg: object            # float32 or bfloat16 (per StepConfig.moment_dtype)
+    exp_avg_sq: object
+    lr: float
+    dar_kind: int = GS_DAR_NONE
+    dar_lambda: float = 0.0
+    dar_clip: float = 0.0
+    reg_mode: int = GS_REG_ADAPTIVE
+
+    @property
+    def dim(self) -> int:
+        return int(self.param.shape[1]) if len(self.param.shape) > 1 else 1
+
+    def to_c(self) -> gs_group:
+        g = gs_group()
+        g.param, g.grad, g.exp_avg, g.exp_avg_sq = (_ptr(self.param), _ptr(self.grad), _ptr(self.exp_avg),
+                                                    _ptr(self.exp_avg_sq))
+        g.dim = self.dim
+        g.dar_kind, g.reg_mode, g.reserved = int(self.dar_kind), int(self.reg_mode), 0
+        g.lr, g.dar_lambda, g.dar_clip = float(self.lr), float(self.dar_lambda), float(self.dar_clip)
+        return g
+
+
+@dataclass
+class StepConfig:
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    reg_norm: float = 1e5
+    seed: int = 0
+    iteration: int = 0
+    moment_dtype: int = GS_MOMENT_F32
+    stochastic_round: bool = True
+    rsr_enable: bool = False
+    schedule: int = GS_SCHED_AUTO
+    rsr_alpha1: float = 0.2
+    rsr_alpha2: float = 0.04
+    rsr_ratio: float = 0.0
+    visible_hint: float = 0.0
+    unit: int = 0
+
+    def to_c(self) -> gs_step_config:
+        c = gs_step_config()
+        c.beta1, c.beta2, c.eps, c.reg_norm = self.beta1, self.beta2, self.eps, self.reg_norm
+        c.seed = int(self.seed) & (2**64 - 1)
+        c.iteration = int(self.iteration)
+        c.moment_dtype = int(self.moment_dtype)
+        c.stochastic_round = int(bool(self.stochastic_round))
+        c.rsr_enable = int(bool(self.rsr_enable))
+        c.schedule = int(self.schedule)
+        c.rsr_alpha1, c.rsr_alpha2, c.rsr_ratio = self.rsr_alpha1, self.rsr_alpha2, self.rsr_ratio
+        c.visible_hint = float(self.visible_hint)
+        c.unit = int(self.unit)
+        return c
+
+
+def _groups_c(groups: Sequence[Group]):
+    arr = (gs_group * max(len(groups), 1))()
+    for k, g in enumerate(groups):
+        arr[k] = g.to_c()
+    return arr
+
+
+def adamw_gs_step(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, visible=None, vis_idx=None,
+                  vis_count=None, stream=None) -> None:
+    """One AdamW-GS step (see include/gsopt.h for the exact contract)."""
+    arr = _groups_c(groups)
+    c = cfg.to_c()
+    _check(_lib.adamw_gs_step(arr, len(groups), int(n), _ptr(visible), _ptr(vis_idx), _ptr(vis_count),
+                              _ptr(step_count), ctypes.byref(c), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Scene:
+    groups: List[Group]
+    n: int
+    step_count: object
+    visible: object = None
+    vis_idx: object = None
+    vis_count: object = None
+    schedule: int = GS_SCHED_AUTO
+    visible_hint: float = 0.0
+
+
+class Batch:
+    """Plan for stepping many scenes in one persistent launch."""
+
+    def __init__(self, scenes: Sequence[Scene]):
+        self._scenes = list(scenes)              # keeps tensors alive
+        self._garr = [_groups_c(s.groups) for s in self._scenes]
+        sarr = (gs_scene * len(self._scenes))()
+        for k, s in enumerate(self._scenes):
+            sarr[k].groups = ctypes.cast(self._garr[k], ctypes.POINTER(gs_group))
+            sarr[k].n_groups = len(s.groups)
+            sarr[k].schedule = int(s.schedule)
+            sarr[k].n = int(s.n)
+            sarr[k].visible, sarr[k].vis_idx, sarr[k].vis_count = (_ptr(s.visible), _ptr(s.vis_idx),
+                                                                   _ptr(s.vis_count))
+            sarr[k].step_count = _ptr(s.step_count)
+            sarr[k].visible_hint = float(s.visible_hint)
+            sarr[k].reserved = 0
+        h = _vp()
+        _check(_lib.gs_batch_create(sarr, len(self._scenes), ctypes.byref(h)))
+        self._h = h
+
+    def schedule(self, s: int) -> int:
+        return int(_lib.gs_batch_scene_schedule(self._h, s))
+
+    def step(self, cfg: StepConfig, stream=None) -> None:
+        adamw_gs_step_batched(self, cfg, stream)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(_lib.gs_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gs_batch_create(scenes: Sequence[Scene]) -> Batch:
+    return Batch(scenes)
+
+
+def adamw_gs_step_batched(batch: Batch, cfg: StepConfig, stream=None) -> None:
+    c = cfg.to_c()
+    _check(_lib.adamw_gs_step_batched(batch._h, ctypes.byref(c), _stream(stream)))
+
+
+def gs_batch_destroy(batch: Batch) -> None:
+    batch.close()
+
+
+# --------------------------------------------------------------------------
+def gs_relocate_workspace_size(n: int) -> int:
+    return int(_lib.gs_relocate_workspace_size(int(n)))
+
+
+def gs_relocate_reset(key, k: int, groups: Sequence[Group], moment_dtype: int, step_count, reset_t: bool,
+                      workspace, selected=None, stream=None) -> None:
+    arr = _groups_c(groups)
+    n = int(key.shape[0])
+    ws_bytes = int(workspace.numel() * workspace.element_size())
+    _check(_lib.gs_relocate_reset(_ptr(key), n, int(k), arr, len(groups), int(moment_dtype), _ptr(step_count),
+                                  int(bool(reset_t)), _ptr(selected), _ptr(workspace), ws_bytes,
+                                  _stream(stream)))
+
+
+def gs_tune(n: int, dims: Sequence[int], visible_fraction: float, moment_dtype: int = GS_MOMENT_F32):
+    """Times the schedules on synthetic buffers; returns (schedule, unit)."""
+    d = (ctypes.c_int32 * len(dims))(*[int(x) for x in dims])
+    s, u = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.gs_tune(int(n), d, len(dims), float(visible_fraction), int(moment_dtype), ctypes.byref(s),
+                        ctypes.byref(u)))
+    return int(s.value), int(u.value)
+
+
+def gs_tune_clear() -> None:
+    _lib.gs_tune_clear()

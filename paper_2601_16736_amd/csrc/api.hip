@@ -1,0 +1,311 @@
+// Host side of the C ABI: argument validation, FP32 constants prepared in
+// double, schedule choice and launches.  Declarations and contracts: gsopt.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "tuner.h"
+
+namespace gs {
+
+namespace {
+
+thread_local std::string t_err;
+
+gs_status fail(gs_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return s;
+}
+
+gs_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(GS_EHIP, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool finite_d(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+uint64_t splitmix_output(uint64_t s, uint64_t k)
+{
+    uint64_t z = s + k * kGamma;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+gs_status set_error(gs_status s, const char* msg)
+{
+    t_err = msg;
+    return s;
+}
+
+void clear_error() { t_err.clear(); }
+
+// Validates one scene's groups and fills the kernel view.  Prefix names the
+// scene in messages.
+gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int32_t moment_dtype,
+                       const gs_step_config* cfg, KScene* out, const char* prefix)
+{
+    if (groups == nullptr) return fail(GS_EINVAL, "%sgroups is NULL", prefix);
+    if (n_groups < 1 || n_groups > GS_MAX_GROUPS)
+        return fail(GS_EINVAL, "%sn_groups = %d, must be in [1, %d]", prefix, n_groups, GS_MAX_GROUPS);
+    const bool bf16 = moment_dtype == GS_MOMENT_BF16;
+    const size_t msz = bf16 ? 2 : 4;
+    for (int g = 0; g < n_groups; ++g) {
+        const gs_group& G = groups[g];
+        if (G.dim < 1 || G.dim > 4096) return fail(GS_EINVAL, "%sgroup %d: dim = %d, must be in [1, 4096]", prefix, g, G.dim);
+        if ((int64_t)G.dim * n >= ((int64_t)1 << 40))
+            return fail(GS_EINVAL, "%sgroup %d: n * dim too large", prefix, g);
+        if (n > 0 && (G.param == nullptr || G.grad == nullptr || G.exp_avg == nullptr || G.exp_avg_sq == nullptr))
+            return fail(GS_EINVAL, "%sgroup %d: param, grad, exp_avg and exp_avg_sq must be non-NULL", prefix, g);
+        if (!aligned(G.param, 4) || !aligned(G.grad, 4) || !aligned(G.exp_avg, msz) || !aligned(G.exp_avg_sq, msz))
+            return fail(GS_EINVAL, "%sgroup %d: misaligned pointer (FP32 arrays need 4 bytes, BF16 moments 2)", prefix, g);
+        if (G.dar_kind < GS_DAR_NONE || G.dar_kind > GS_DAR_LOGSCALE_EXP)
+            return fail(GS_EINVAL, "%sgroup %d: unknown dar_kind %d", prefix, g, G.dar_kind);
+        if (G.reg_mode < GS_REG_ADAPTIVE || G.reg_mode > GS_REG_CONSTANT_CLIPPED)
+            return fail(GS_EINVAL, "%sgroup %d: unknown reg_mode %d", prefix, g, G.reg_mode);
+        if (G.reserved != 0) return fail(GS_EINVAL, "%sgroup %d: reserved must be 0", prefix, g);
+        if (!finite_d(G.lr)) return fail(GS_EINVAL, "%sgroup %d: lr must be finite", prefix, g);
+        if (!(G.dar_lambda >= 0.0) || !finite_d(G.dar_lambda))
+            return fail(GS_EINVAL, "%sgroup %d: dar_lambda must be finite and >= 0", prefix, g);
+        if (!(G.dar_clip >= 0.0)) return fail(GS_EINVAL, "%sgroup %d: dar_clip must be >= 0", prefix, g);
+
+        KGroup& K = out->g[g];
+        K.param = G.param;
+        K.grad = G.grad;
+        K.m = G.exp_avg;
+        K.v = G.exp_avg_sq;
+        K.dim = G.dim;
+        int vec = 1;
+        if (G.dim % 4 == 0 && aligned(G.param, 16) && aligned(G.grad, 16) && aligned(G.exp_avg, 4 * msz) &&
+            aligned(G.exp_avg_sq, 4 * msz))
+            vec = 4;
+        else if (G.dim % 2 == 0 && aligned(G.param, 8) && aligned(G.grad, 8) && aligned(G.exp_avg, 2 * msz) &&
+                 aligned(G.exp_avg_sq, 2 * msz))
+            vec = 2;
+        K.vec = vec;
+        K.cpr = G.dim / vec;
+        K.lr = (float)G.lr;
+        K.dar_kind = G.dar_kind;
+        K.reg_mode = G.reg_mode;
+        if (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
+            K.dar_scale = (float)(G.dar_lambda / cfg->reg_norm);
+        else
+            K.dar_scale = (float)G.dar_lambda;
+        K.dar_clip = std::isinf(G.dar_clip) ? INFINITY : (float)G.dar_clip;
+        K.sr_s1 = splitmix_output(cfg->seed, kTagSrStep + (uint64_t)g + 1);
+        K.rsr_sr_s1 = splitmix_output(cfg->seed, kTagSrRsr + (uint64_t)g + 1);
+    }
+    for (int g = n_groups; g < GS_MAX_GROUPS; ++g) memset(&out->g[g], 0, sizeof(KGroup));
+    out->n_groups = n_groups;
+    out->bf16 = bf16 ? 1 : 0;
+    out->n = n;
+    return GS_OK;
+}
+
+gs_status build_hyper(const gs_step_config* cfg, bool need_reg_norm, KHyper* h)
+{
+    if (cfg == nullptr) return fail(GS_EINVAL, "cfg is NULL");
+    if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0)) return fail(GS_EINVAL, "beta1 = %g, must be in [0, 1)", cfg->beta1);
+    if (!(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0)) return fail(GS_EINVAL, "beta2 = %g, must be in [0, 1)", cfg->beta2);
+    if (!(cfg->eps > 0.0) || !finite_d(cfg->eps) || !((float)cfg->eps > 0.0f))
+        return fail(GS_EINVAL, "eps = %g, must be > 0 and representable in FP32", cfg->eps);
+    if (need_reg_norm && !(cfg->reg_norm > 0.0 && finite_d(cfg->reg_norm)))
+        return fail(GS_EINVAL, "reg_norm = %g, must be finite and > 0 for adaptive DAR groups", cfg->reg_norm);
+    if (cfg->moment_dtype != GS_MOMENT_F32 && cfg->moment_dtype != GS_MOMENT_BF16)
+        return fail(GS_EINVAL, "unknown moment_dtype %d", cfg->moment_dtype);
+    if (cfg->iteration < 0) return fail(GS_EINVAL, "iteration must be >= 0");
+    if (cfg->rsr_enable) {
+        if (!(cfg->rsr_alpha1 >= 0.0 && cfg->rsr_alpha1 < 1.0))
+            return fail(GS_EINVAL, "rsr_alpha1 = %g, must be in [0, 1)", cfg->rsr_alpha1);
+        if (!(cfg->rsr_alpha2 >= 0.0 && cfg->rsr_alpha2 < 1.0))
+            return fail(GS_EINVAL, "rsr_alpha2 = %g, must be in [0, 1)", cfg->rsr_alpha2);
+        if (!(cfg->rsr_ratio >= 0.0 && cfg->rsr_ratio <= 1.0))
+            return fail(GS_EINVAL, "rsr_ratio = %g, must be in [0, 1]", cfg->rsr_ratio);
+    }
+    h->beta1 = (float)cfg->beta1;
+    h->omb1 = (float)(1.0 - cfg->beta1);
+    h->beta2 = (float)cfg->beta2;
+    h->omb2 = (float)(1.0 - cfg->beta2);
+    h->logb1 = cfg->beta1 > 0.0 ? (float)std::log(cfg->beta1) : -INFINITY;
+    h->logb2 = cfg->beta2 > 0.0 ? (float)std::log(cfg->beta2) : -INFINITY;
+    h->eps = (float)cfg->eps;
+    h->rsr_a1 = (float)cfg->rsr_alpha1;
+    h->rsr_a2 = (float)cfg->rsr_alpha2;
+    h->c1_rsr = (float)(cfg->beta1 * cfg->rsr_alpha1);
+    h->c2_rsr = (float)(cfg->beta2 * cfg->rsr_alpha2);
+    h->sr = (cfg->moment_dtype == GS_MOMENT_BF16 && cfg->stochastic_round) ? 1 : 0;
+    uint64_t thr = 0;
+    if (cfg->rsr_enable) {
+        if (cfg->rsr_ratio >= 1.0) thr = (uint64_t)1 << 32;
+        else if (cfg->rsr_ratio > 0.0) thr = (uint64_t)std::floor(cfg->rsr_ratio * 4294967296.0);
+    }
+    h->rsr_thr = thr;
+    h->rsr_s1 = splitmix_output(cfg->seed, kTagRsr + 1);
+    h->iteration = cfg->iteration;
+    return GS_OK;
+}
+
+bool any_adaptive(const gs_group* groups, int32_t n_groups)
+{
+    if (groups == nullptr) return false;
+    for (int g = 0; g < n_groups && g < GS_MAX_GROUPS; ++g)
+        if (groups[g].dar_kind != GS_DAR_NONE && groups[g].reg_mode == GS_REG_ADAPTIVE) return true;
+    return false;
+}
+
+bool valid_unit(int sched, int unit)
+{
+    if (sched == kSchedCompacted) return unit == 64 || unit == 128 || unit == 256 || unit == 512;
+    if (sched == kSchedMasked) return unit == 128 || unit == 256 || unit == 512;
+    if (sched == kSchedDense) return unit == 256 || unit == 512;
+    return false;
+}
+
+int default_unit(int sched) { return sched == kSchedCompacted ? 128 : 512; }
+
+// Resolves the schedule and unit of a scene from what the caller supplied.
+gs_status resolve_schedule(int requested, int unit, float hint, int64_t n, int n_groups, const int32_t* dims,
+                           int dtype, const uint8_t* mask, const int32_t* idx, const int32_t* count,
+                           int* sched_out, int* unit_out, const char* prefix)
+{
+    int sched = requested;
+    if (sched == GS_SCHED_AUTO) {
+        int tuned_s = 0, tuned_u = 0;
+        if (hint > 0.0f && tuner_lookup(n, hint, dtype, &tuned_s, &tuned_u) &&
+            ((tuned_s == kSchedCompacted && idx && count) || (tuned_s == kSchedMasked && mask))) {
+            sched = tuned_s;
+            if (unit == 0) unit = tuned_u;
+        } else if (idx != nullptr && count != nullptr) {
+            sched = kSchedCompacted;
+        } else if (mask != nullptr) {
+            sched = kSchedMasked;
+        } else {
+            sched = kSchedDense;
+        }
+    }
+    (void)n_groups;
+    (void)dims;
+    if (sched == kSchedCompacted && (idx == nullptr || count == nullptr))
+        return fail(GS_EINVAL, "%scompacted schedule needs vis_idx and vis_count", prefix);
+    if (sched == kSchedMasked && mask == nullptr) return fail(GS_EINVAL, "%smasked schedule needs visible", prefix);
+    if (sched != kSchedCompacted && sched != kSchedMasked && sched != kSchedDense)
+        return fail(GS_EINVAL, "%sunknown schedule %d", prefix, requested);
+    if (unit == 0) unit = default_unit(sched);
+    if (!valid_unit(sched, unit)) return fail(GS_EINVAL, "%sunit %d not available for schedule %d", prefix, unit, sched);
+    if (sched == kSchedCompacted && !aligned(idx, 4)) return fail(GS_EINVAL, "%svis_idx misaligned", prefix);
+    *sched_out = sched;
+    *unit_out = unit;
+    return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return t_err.c_str(); }
+
+int32_t gs_version(void) { return GSOPT_VERSION; }
+
+double gs_reg_norm(double n_pixels)
+{
+    if (!(n_pixels >= 1.0) || !std::isfinite(n_pixels)) return 0.0;
+    uint64_t v = (uint64_t)n_pixels;
+    uint64_t p = 1;
+    while (v / p >= 10) p *= 10;
+    return (double)((v / p) * p) / 10.0;
+}
+
+gs_status gs_visibility(const float* means, const float* radius, int64_t n, const gs_camera* cam, uint8_t* mask,
+                        int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    if (cam == nullptr) return fail(GS_EINVAL, "cam is NULL");
+    if (mask == nullptr && vis_idx == nullptr) return fail(GS_EINVAL, "mask and vis_idx are both NULL");
+    if (vis_idx != nullptr && vis_count == nullptr) return fail(GS_EINVAL, "vis_idx needs vis_count");
+    if (n > 0 && means == nullptr) return fail(GS_EINVAL, "means is NULL");
+    if (!aligned(means, 4) || !aligned(radius, 4) || !aligned(vis_idx, 4) || !aligned(vis_count, 4))
+        return fail(GS_EINVAL, "misaligned pointer (4-byte alignment required)");
+    if (cam->width < 1 || cam->height < 1) return fail(GS_EINVAL, "camera width/height must be >= 1");
+    if (!(cam->z_near >= 0.0f) || !(cam->z_far > cam->z_near))
+        return fail(GS_EINVAL, "camera needs 0 <= z_near < z_far");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(cam->view[k])) return fail(GS_EINVAL, "camera view matrix must be finite");
+    if (!std::isfinite(cam->fx) || !std::isfinite(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+        return fail(GS_EINVAL, "camera intrinsics must be finite");
+    KCamera k;
+    memcpy(k.R, cam->view, sizeof k.R);
+    k.fx = cam->fx;
+    k.fy = cam->fy;
+    k.cx = cam->cx;
+    k.cy = cam->cy;
+    k.W = (float)cam->width;
+    k.H = (float)cam->height;
+    k.z_near = cam->z_near;
+    k.z_far = cam->z_far;
+    k.r_min = cam->r_min_px;
+    k.f_max = cam->fx > cam->fy ? cam->fx : cam->fy;
+    const hipError_t e = launch_visibility(means, radius, n, k, mask, vis_idx, vis_count, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_visibility launch");
+}
+
+gs_status gs_compact(const uint8_t* mask, int64_t n, int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    if (vis_idx == nullptr || vis_count == nullptr) return fail(GS_EINVAL, "vis_idx and vis_count are required");
+    if (n > 0 && mask == nullptr) return fail(GS_EINVAL, "mask is NULL");
+    if (!aligned(vis_idx, 4) || !aligned(vis_count, 4)) return fail(GS_EINVAL, "misaligned pointer");
+    const hipError_t e = launch_compact(mask, n, vis_idx, vis_count, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_compact launch");
+}
+
+gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, const uint8_t* visible,
+                        const int32_t* vis_idx, const int32_t* vis_count, int32_t* step_count,
+                        const gs_step_config* cfg, hipStream_t stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    if (n > 0 && step_count == nullptr) return fail(GS_EINVAL, "step_count is NULL");
+    if (!aligned(step_count, 4) || !aligned(vis_count, 4)) return fail(GS_EINVAL, "misaligned step_count/vis_count");
+    KHyper h;
+    gs_status st = build_hyper(cfg, any_adaptive(groups, n_groups), &h);
+    if (st != GS_OK) return st;
+    KScene s;
+    memset(&s, 0, sizeof s);
+    st = build_groups(groups, n_groups, n, cfg->moment_dtype, cfg, &s, "");
+    if (st != GS_OK) return st;
+    int32_t dims[GS_MAX_GROUPS];
+    for (int g = 0; g < n_groups; ++g) dims[g] = groups[g].dim;
+    int sched = 0, unit = 0;
+    st = resolve_schedule(cfg->schedule, cfg->unit, cfg->visible_hint, n, n_groups, dims, cfg->moment_dtype, visible,
+                          vis_idx, vis_count, &sched, &unit, "");
+    if (st != GS_OK) return st;
+    if (cfg->rsr_enable && h.rsr_thr > 0 && sched != kSchedDense && visible == nullptr)
+        return fail(GS_EINVAL, "RSR with a sparse schedule needs the visibility mask (to rescale invisible rows)");
+    s.sched = sched;
+    s.unit = unit;
+    s.mask = visible;
+    s.idx = vis_idx;
+    s.count = vis_count;
+    s.t = step_count;
+    const hipError_t e = launch_step(s, h, cfg->rsr_enable != 0 && h.rsr_thr > 0, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step launch");
+}
+
+}  // extern "C"

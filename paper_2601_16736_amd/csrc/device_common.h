@@ -1,0 +1,362 @@
+// Device-side building blocks of the AdamW-GS step kernels (gfx950, wave64).
+//
+// Work is organised per wavefront: a wave takes one "unit" (a window of the
+// mask, or a slice of the visible-index list), stages the unit's visible row
+// indices and per-row bias corrections in its own slice of LDS, then sweeps
+// each attribute group once.  Inside a group the wave's 64 lanes walk the
+// flattened (row, chunk) space of the staged rows, so consecutive lanes touch
+// consecutive 4/8/16-byte chunks of one row before moving to the next row:
+// every group is one coalesced read-modify-write pass.
+#pragma once
+
+#include "internal.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- draws
+// SplitMix64 output function and stream (Steele, Lea & Flood 2014): the
+// k-th output of the stream with state s is mix64(s + k * gamma).
+__device__ __forceinline__ uint64_t d_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t d_splitmix(uint64_t s, uint64_t k) { return d_mix64(s + k * kGamma); }
+
+// ---------------------------------------------------------------- bf16 storage
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// round-to-nearest-even; NaN stays a quiet NaN
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (b >> 16) | 0x40u;
+    return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+
+// stochastic rounding: add 16 random bits below the kept bits, truncate
+__device__ __forceinline__ uint32_t f32_to_bf16_sr(float x, uint32_t r16)
+{
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7F800000u) == 0x7F800000u) return (b >> 16) | ((b & 0x007FFFFFu) ? 0x40u : 0u);
+    return (b + r16) >> 16;
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// number of set bits of `mask` in lanes below this one
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ---------------------------------------------------------------- vector access
+template <int V> __device__ __forceinline__ void load_f(const float* p, float* x)
+{
+    if constexpr (V == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+    } else if constexpr (V == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        x[0] = t.x; x[1] = t.y;
+    } else {
+        x[0] = *p;
+    }
+}
+
+template <int V> __device__ __forceinline__ void store_f(float* p, const float* x)
+{
+    if constexpr (V == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(x[0], x[1], x[2], x[3]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(x[0], x[1]);
+    } else {
+        *p = x[0];
+    }
+}
+
+template <int V> __device__ __forceinline__ void load_h(const uint16_t* p, float* x)
+{
+    if constexpr (V == 4) {
+        const uint2 t = *reinterpret_cast<const uint2*>(p);
+        x[0] = bf16_to_f32(t.x & 0xFFFFu); x[1] = bf16_to_f32(t.x >> 16);
+        x[2] = bf16_to_f32(t.y & 0xFFFFu); x[3] = bf16_to_f32(t.y >> 16);
+    } else if constexpr (V == 2) {
+        const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+        x[0] = bf16_to_f32(t & 0xFFFFu); x[1] = bf16_to_f32(t >> 16);
+    } else {
+        x[0] = bf16_to_f32(*p);
+    }
+}
+
+template <int V> __device__ __forceinline__ void store_h(uint16_t* p, const uint32_t* h)
+{
+    if constexpr (V == 4) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<uint32_t*>(p) = h[0] | (h[1] << 16);
+    } else {
+        *p = (uint16_t)h[0];
+    }
+}
+
+template <bool BF16, int V> __device__ __forceinline__ void load_moment(const void* base, int64_t e, float* x)
+{
+    if constexpr (BF16) load_h<V>(static_cast<const uint16_t*>(base) + e, x);
+    else load_f<V>(static_cast<const float*>(base) + e, x);
+}
+
+// Stores m and v of V consecutive elements starting at element e.  BF16:
+// element e+q takes its rounding bits from draw (e+q+1) of stream s2.
+template <bool BF16, int V>
+__device__ __forceinline__ void store_moments(void* mb, void* vb, int64_t e, const float* m, const float* v,
+                                              bool sr, uint64_t s2)
+{
+    if constexpr (BF16) {
+        uint32_t hm[V], hv[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            if (sr) {
+                const uint64_t r = d_splitmix(s2, (uint64_t)(e + q) + 1);
+                hm[q] = f32_to_bf16_sr(m[q], (uint32_t)(r >> 48));
+                hv[q] = f32_to_bf16_sr(v[q], (uint32_t)(r >> 32) & 0xFFFFu);
+            } else {
+                hm[q] = f32_to_bf16_rne(m[q]);
+                hv[q] = f32_to_bf16_rne(v[q]);
+            }
+        }
+        store_h<V>(static_cast<uint16_t*>(mb) + e, hm);
+        store_h<V>(static_cast<uint16_t*>(vb) + e, hv);
+    } else {
+        store_f<V>(static_cast<float*>(mb) + e, m);
+        store_f<V>(static_cast<float*>(vb) + e, v);
+    }
+}
+
+// ---------------------------------------------------------------- the update
+// Regulariser term added to the Adam direction u (DAR update equation and
+// the AdamW-style variants).  R' is the activation derivative at the
+// pre-update theta: sigma(tau)(1 - sigma(tau)), computed in the equivalent
+// form e/(1+e)^2 with e = exp(-|tau|) (no cancellation), or exp(kappa).
+__device__ __forceinline__ float reg_term(int kind, int mode, float scale, float clip, float th, float d)
+{
+    float R;
+    if (kind == GS_DAR_OPACITY_SIGMOID) {
+        const float e = expf(-fabsf(th));
+        const float q = 1.0f + e;
+        R = e / (q * q);
+    } else {
+        R = expf(th);
+    }
+    if (mode == GS_REG_ADAPTIVE) return fminf(scale * R / d, clip);
+    if (mode == GS_REG_CONSTANT) return scale * R;
+    return fminf(scale * R, clip);
+}
+
+// One group's read-modify-write pass over the wave's staged rows.
+template <bool BF16, int V>
+__device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int nrows,
+                                           const int* s_row, const float* s_rb1, const float* s_rsb2,
+                                           int lane, uint64_t sr_s2)
+{
+    const int cpr = G.cpr;
+    const int dim = G.dim;
+    const int items = nrows * cpr;
+    int r = lane / cpr;
+    int c = lane - r * cpr;
+    const int dr = kWave / cpr;
+    const int dc = kWave - dr * cpr;
+    const bool dar = G.dar_kind != GS_DAR_NONE;
+    for (int k = lane; k < items; k += kWave) {
+        const int raw = s_row[r];
+        const int prim = raw & 0x7FFFFFFF;
+        // a row in this iteration's Re-State sample decays by alpha before the
+        // moment update: beta*(alpha*m) folded into (beta*alpha)*m
+        const float c1 = raw < 0 ? H.c1_rsr : H.beta1;
+        const float c2 = raw < 0 ? H.c2_rsr : H.beta2;
+        const float rb1 = s_rb1[r];
+        const float rsb2 = s_rsb2[r];
+        const int64_t e = (int64_t)prim * dim + c * V;
+        float th[V], g[V], m[V], v[V];
+        load_f<V>(G.param + e, th);
+        load_f<V>(G.grad + e, g);
+        load_moment<BF16, V>(G.m, e, m);
+        load_moment<BF16, V>(G.v, e, v);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const float mm = c1 * m[q] + H.omb1 * g[q];
+            const float vv = c2 * v[q] + H.omb2 * (g[q] * g[q]);
+            const float d = __fsqrt_rn(vv) * rsb2 + H.eps;       // sqrt(v / b2) + eps
+            float u = (mm * rb1) / d;                             // (m / b1) / d
+            if (dar) u += reg_term(G.dar_kind, G.reg_mode, G.dar_scale, G.dar_clip, th[q], d);
+            th[q] = th[q] - G.lr * u;
+            m[q] = mm;
+            v[q] = vv;
+        }
+        store_f<V>(G.param + e, th);
+        store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
+        r += dr;
+        c += dc;
+        if (c >= cpr) { c -= cpr; ++r; }
+    }
+}
+
+// One group's Re-State rescale of the wave's staged rows: m <- a1 m, v <- a2 v.
+template <bool BF16, int V>
+__device__ __forceinline__ void rsr_group(const KGroup& G, const KHyper& H, int nrows, const int* s_row,
+                                          int lane, uint64_t sr_s2)
+{
+    const int cpr = G.cpr;
+    const int dim = G.dim;
+    const int items = nrows * cpr;
+    int r = lane / cpr;
+    int c = lane - r * cpr;
+    const int dr = kWave / cpr;
+    const int dc = kWave - dr * cpr;
+    for (int k = lane; k < items; k += kWave) {
+        const int64_t e = (int64_t)s_row[r] * dim + c * V;
+        float m[V], v[V];
+        load_moment<BF16, V>(G.m, e, m);
+        load_moment<BF16, V>(G.v, e, v);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            m[q] = H.rsr_a1 * m[q];
+            v[q] = H.rsr_a2 * v[q];
+        }
+        store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
+        r += dr;
+        c += dc;
+        if (c >= cpr) { c -= cpr; ++r; }
+    }
+}
+
+// ---------------------------------------------------------------- staging
+// Rows of a window [w0, w0 + UNIT) that pass the mask (mask == nullptr: all
+// rows below n), in ascending order.  Returns the row count.
+template <int UNIT>
+__device__ __forceinline__ int build_rows_window(const uint8_t* mask, int64_t n, int64_t w0, int* s_row,
+                                                 int lane)
+{
+    bool vis[UNIT / kWave];
+#pragma unroll
+    for (int b = 0; b < UNIT / kWave; ++b) {
+        const int64_t i = w0 + b * kWave + lane;
+        vis[b] = i < n;
+        if (mask != nullptr && vis[b]) vis[b] = mask[i] != 0;
+    }
+    int nrows = 0;
+#pragma unroll
+    for (int b = 0; b < UNIT / kWave; ++b) {
+        const uint64_t bal = __ballot(vis[b]);
+        if (vis[b]) s_row[nrows + lanes_below(bal)] = (int)(w0 + b * kWave + lane);
+        nrows += __popcll(bal);
+    }
+    return nrows;
+}
+
+// Re-State sample: primitive i is sampled iff the top 32 bits of draw (i+1)
+// of stream s2 are below thr.
+__device__ __forceinline__ bool rsr_sampled(uint64_t s2, uint64_t thr, int64_t i)
+{
+    return (d_splitmix(s2, (uint64_t)i + 1) >> 32) < thr;
+}
+
+// Sampled rows of a window that the step itself does not visit (mask == 0).
+template <int UNIT>
+__device__ __forceinline__ int build_rows_sampled(const uint8_t* mask, int64_t n, int64_t w0, uint64_t s2,
+                                                  uint64_t thr, int* s_row, int lane)
+{
+    int nrows = 0;
+#pragma unroll
+    for (int b = 0; b < UNIT / kWave; ++b) {
+        const int64_t i = w0 + b * kWave + lane;
+        const bool pick = i < n && mask[i] == 0 && rsr_sampled(s2, thr, i);
+        const uint64_t bal = __ballot(pick);
+        if (pick) s_row[nrows + lanes_below(bal)] = (int)i;
+        nrows += __popcll(bal);
+    }
+    return nrows;
+}
+
+// Entries [base, base + UNIT) of the visible-index list (cnt entries in all).
+// Entries outside [0, n) are dropped, so a corrupt list cannot send the
+// step outside the arrays.
+template <int UNIT>
+__device__ __forceinline__ int build_rows_slice(const int32_t* idx, int cnt, int64_t n, int64_t base, int* s_row,
+                                                int lane)
+{
+    const int avail = (int)min((int64_t)UNIT, (int64_t)cnt - base);
+    int32_t v[UNIT / kWave];
+#pragma unroll
+    for (int b = 0; b < UNIT / kWave; ++b) {
+        const int j = b * kWave + lane;
+        v[b] = j < avail ? idx[base + j] : -1;
+    }
+    int nrows = 0;
+#pragma unroll
+    for (int b = 0; b < UNIT / kWave; ++b) {
+        const bool ok = v[b] >= 0 && v[b] < n;
+        const uint64_t bal = __ballot(ok);
+        if (ok) s_row[nrows + lanes_below(bal)] = v[b];
+        nrows += __popcll(bal);
+    }
+    return nrows;
+}
+
+// t_i <- t_i + 1 for each staged row and its bias corrections:
+// 1/(1 - beta1^t) and 1/sqrt(1 - beta2^t), with 1 - beta^t = -expm1(t log beta).
+// A row in the Re-State sample gets its sign bit set (indices are < 2^31).
+__device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_rb1, float* s_rsb2,
+                                                int32_t* t, const KHyper& H, int lane)
+{
+    const uint64_t rsr_s2 = d_splitmix(H.rsr_s1, (uint64_t)H.iteration + 1);
+    for (int j = lane; j < nrows; j += kWave) {
+        const int i = s_row[j];
+        if (H.rsr_thr != 0 && rsr_sampled(rsr_s2, H.rsr_thr, i)) s_row[j] = (int)((uint32_t)i | 0x80000000u);
+        const int tn = t[i] + 1;
+        t[i] = tn;
+        const float ft = (float)tn;
+        const float b1 = -expm1f(ft * H.logb1);
+        const float b2 = -expm1f(ft * H.logb2);
+        s_rb1[j] = 1.0f / b1;
+        s_rsb2[j] = 1.0f / __fsqrt_rn(b2);
+    }
+}
+
+// Every group's pass over the staged rows.
+template <bool BF16>
+__device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, int nrows, const int* s_row,
+                                                const float* s_rb1, const float* s_rsb2, int lane)
+{
+    for (int gi = 0; gi < S.n_groups; ++gi) {
+        const KGroup& G = S.g[gi];
+        const uint64_t s2 = BF16 ? d_splitmix(G.sr_s1, (uint64_t)H.iteration + 1) : 0;
+        if (G.vec == 4) step_group<BF16, 4>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        else if (G.vec == 2) step_group<BF16, 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        else step_group<BF16, 1>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+    }
+}
+
+template <bool BF16>
+__device__ __forceinline__ void rsr_all_groups(const KScene& S, const KHyper& H, int nrows, const int* s_row,
+                                               int lane)
+{
+    for (int gi = 0; gi < S.n_groups; ++gi) {
+        const KGroup& G = S.g[gi];
+        const uint64_t s2 = BF16 ? d_splitmix(G.rsr_sr_s1, (uint64_t)H.iteration + 1) : 0;
+        if (G.vec == 4) rsr_group<BF16, 4>(G, H, nrows, s_row, lane, s2);
+        else if (G.vec == 2) rsr_group<BF16, 2>(G, H, nrows, s_row, lane, s2);
+        else rsr_group<BF16, 1>(G, H, nrows, s_row, lane, s2);
+    }
+}
+
+}  // namespace gs

@@ -1,0 +1,93 @@
+// Internal declarations of the gfx950 AdamW-GS library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsopt.h"
+
+namespace gs {
+
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kCap = 512;            // max rows a wave stages per unit
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+enum : uint64_t { kTagRsr = 1, kTagSrStep = 16, kTagSrRsr = 32 };
+enum : int { kSchedCompacted = 1, kSchedMasked = 2, kSchedDense = 3 };
+
+// One attribute group as the kernels see it.
+struct KGroup {
+    float* param;
+    const float* grad;
+    void* m;
+    void* v;
+    int32_t dim;
+    int32_t vec;         // elements per access: 4, 2 or 1
+    int32_t cpr;         // accesses per row = dim / vec
+    float lr;
+    int32_t dar_kind;
+    int32_t reg_mode;
+    float dar_scale;     // lambda / N_I' (adaptive) or lambda (constant modes)
+    float dar_clip;
+    uint64_t sr_s1;      // SplitMix state after the group's step-rounding tag
+    uint64_t rsr_sr_s1;  // same for the RSR-rounding tag
+};
+
+// Per-call scalars.
+struct KHyper {
+    float beta1, omb1, beta2, omb2;   // beta and (1 - beta), both rounded from double
+    float logb1, logb2;               // log(beta) rounded from double (-inf for beta = 0)
+    float eps;
+    float rsr_a1, rsr_a2;
+    float c1_rsr, c2_rsr;             // beta1*alpha1, beta2*alpha2: moment decay of a sampled visible row
+    int32_t sr;                       // stochastic rounding of BF16 moments
+    uint64_t rsr_thr;                 // sampled iff draw >> 32 < rsr_thr
+    uint64_t rsr_s1;                  // sampling stream state after the RSR tag (iteration applied on device)
+    int64_t iteration;
+};
+
+// One scene: its groups, visibility inputs and schedule.
+struct KScene {
+    KGroup g[GS_MAX_GROUPS];
+    int32_t n_groups;
+    int32_t sched;
+    int32_t unit;                      // rows (compacted) or primitives (masked/dense) per wave unit
+    int32_t bf16;
+    int64_t n;
+    const uint8_t* mask;
+    const int32_t* idx;
+    const int32_t* count;
+    int32_t* t;
+};
+
+struct KCamera {
+    float R[12];
+    float fx, fy, cx, cy;
+    float W, H;
+    float z_near, z_far;
+    float r_min, f_max;
+};
+
+// host-side helpers shared by the library's translation units
+uint64_t splitmix_output(uint64_t s, uint64_t k);
+
+hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
+                             uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream);
+hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream);
+hipError_t launch_step(const KScene& s, const KHyper& h, bool rsr, hipStream_t stream);
+hipError_t launch_rsr(const KScene& s, const KHyper& h, hipStream_t stream);
+size_t step_kernel_units(const KScene& s);
+
+// batched
+struct BatchDevice;  // defined in batched.hip
+hipError_t launch_batched(const KScene* d_scenes, int32_t n_scenes, const int64_t* d_unit_prefix_max,
+                          int32_t* d_queue, int grid, const KHyper& h, int rsr, hipStream_t stream);
+
+// relocation
+size_t relocate_workspace_bytes(int64_t n);
+hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene& s, int reset_t,
+                           int32_t* selected, void* ws, hipStream_t stream);
+
+}  // namespace gs

@@ -1,0 +1,126 @@
+// Single-scene AdamW-GS step kernels: the fused Sparse-Adam + DAR pass and
+// the Re-State Regularization pass (gfx950).
+#include "device_common.h"
+
+namespace gs {
+
+// One wave per unit.  SCHED picks where the unit's rows come from:
+//   compacted: entries [unit*UNIT, unit*UNIT + UNIT) of the visible-index list
+//   masked:    visible primitives of the window [unit*UNIT, unit*UNIT + UNIT)
+//   dense:     every primitive of that window (V = 1)
+// The grid covers the largest possible unit count; waves past the end exit.
+template <bool BF16, int SCHED, int UNIT>
+__global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
+{
+    __shared__ int s_row[kWavesPerBlock][UNIT];
+    __shared__ float s_rb1[kWavesPerBlock][UNIT];
+    __shared__ float s_rsb2[kWavesPerBlock][UNIT];
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    int nrows;
+    if constexpr (SCHED == kSchedCompacted) {
+        const int cnt = (int)min((int64_t)*S.count, S.n);   // the list holds at most n entries
+        const int64_t base = unit * UNIT;
+        if (base >= cnt) return;
+        nrows = build_rows_slice<UNIT>(S.idx, cnt, S.n, base, s_row[wave], lane);
+    } else {
+        const int64_t w0 = unit * UNIT;
+        if (w0 >= S.n) return;
+        nrows = build_rows_window<UNIT>(SCHED == kSchedMasked ? S.mask : nullptr, S.n, w0, s_row[wave], lane);
+    }
+    if (nrows == 0) return;
+    wave_sync();
+    stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H, lane);
+    wave_sync();
+    step_all_groups<BF16>(S, H, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+}
+
+// Re-State pass over the primitives the step does not visit (mask == 0):
+// each wave takes a window of 512, stages the sampled invisible rows and
+// rescales their moments in every group.  Sampled visible rows are rescaled
+// inside the step kernel, in registers, before their moment update.
+constexpr int kRsrUnit = 512;
+
+template <bool BF16>
+__global__ __launch_bounds__(kBlock) void rsr_kernel(KScene S, KHyper H)
+{
+    __shared__ int s_row[kWavesPerBlock][kRsrUnit];
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRsrUnit;
+    if (w0 >= S.n) return;
+    const uint64_t s2 = d_splitmix(H.rsr_s1, (uint64_t)H.iteration + 1);
+    const int nrows = build_rows_sampled<kRsrUnit>(S.mask, S.n, w0, s2, H.rsr_thr, s_row[wave], lane);
+    if (nrows == 0) return;
+    wave_sync();
+    rsr_all_groups<BF16>(S, H, nrows, s_row[wave], lane);
+}
+
+namespace {
+
+using StepFn = void (*)(KScene, KHyper);
+
+template <bool BF16>
+StepFn pick(int sched, int unit)
+{
+    if (sched == kSchedCompacted) {
+        switch (unit) {
+        case 64: return step_kernel<BF16, kSchedCompacted, 64>;
+        case 128: return step_kernel<BF16, kSchedCompacted, 128>;
+        case 256: return step_kernel<BF16, kSchedCompacted, 256>;
+        case 512: return step_kernel<BF16, kSchedCompacted, 512>;
+        default: return nullptr;
+        }
+    }
+    if (sched == kSchedMasked) {
+        switch (unit) {
+        case 128: return step_kernel<BF16, kSchedMasked, 128>;
+        case 256: return step_kernel<BF16, kSchedMasked, 256>;
+        case 512: return step_kernel<BF16, kSchedMasked, 512>;
+        default: return nullptr;
+        }
+    }
+    if (sched == kSchedDense) {
+        switch (unit) {
+        case 256: return step_kernel<BF16, kSchedDense, 256>;
+        case 512: return step_kernel<BF16, kSchedDense, 512>;
+        default: return nullptr;
+        }
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+size_t step_kernel_units(const KScene& s)
+{
+    return (size_t)((s.n + s.unit - 1) / s.unit);
+}
+
+hipError_t launch_step(const KScene& s, const KHyper& h, bool rsr, hipStream_t stream)
+{
+    if (s.n == 0) return hipSuccess;
+    if (rsr && s.sched != kSchedDense) {
+        const hipError_t e = launch_rsr(s, h, stream);
+        if (e != hipSuccess) return e;
+    }
+    StepFn fn = s.bf16 ? pick<true>(s.sched, s.unit) : pick<false>(s.sched, s.unit);
+    if (fn == nullptr) return hipErrorInvalidValue;
+    const size_t units = step_kernel_units(s);
+    const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, s, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_rsr(const KScene& s, const KHyper& h, hipStream_t stream)
+{
+    if (s.n == 0 || h.rsr_thr == 0 || s.mask == nullptr) return hipSuccess;
+    const size_t units = (size_t)((s.n + kRsrUnit - 1) / kRsrUnit);
+    const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (s.bf16) hipLaunchKernelGGL(rsr_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
+    else hipLaunchKernelGGL(rsr_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
+    return hipGetLastError();
+}
+
+}  // namespace gs

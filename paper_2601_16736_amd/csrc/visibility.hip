@@ -1,0 +1,139 @@
+// Per-view visibility (frustum/radius cull of the projected means) and
+// compaction of the visible indices (gfx950).
+//
+// Each block of 256 threads covers 1024 consecutive primitives in four
+// rounds.  Per round a wave ballots its 64 predicates; the block adds up its
+// 16 wave counts and reserves one contiguous range of the index list with a
+// single atomic, so the list holds ascending runs of up to 1024 primitives.
+#include "device_common.h"
+
+namespace gs {
+
+constexpr int kVisRounds = 4;
+constexpr int kVisPerBlock = kBlock * kVisRounds;
+
+// The FP32 predicate, one rounding per operation in the stated order (no
+// contraction into fused multiply-add).
+__device__ __forceinline__ bool visible_pred(float x, float y, float z, const float* rho, const KCamera& c)
+{
+#pragma clang fp contract(off)
+    const float px = ((c.R[0] * x + c.R[1] * y) + c.R[2] * z) + c.R[3];
+    const float py = ((c.R[4] * x + c.R[5] * y) + c.R[6] * z) + c.R[7];
+    const float pz = ((c.R[8] * x + c.R[9] * y) + c.R[10] * z) + c.R[11];
+    if (!(pz > c.z_near)) return false;
+    if (!(pz < c.z_far)) return false;
+    const float u = (c.fx * px) / pz + c.cx;
+    const float v = (c.fy * py) / pz + c.cy;
+    float r = 0.0f;
+    if (rho != nullptr) {
+        r = (c.f_max * *rho) / pz;
+        if (!(r >= c.r_min)) return false;
+    }
+    if (!(u + r >= 0.0f)) return false;
+    if (!(u - r <= c.W)) return false;
+    if (!(v + r >= 0.0f)) return false;
+    if (!(v - r <= c.H)) return false;
+    return true;
+}
+
+// Appends the visible primitives of this block (flags per round) to idx.
+__device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int64_t first, int32_t* idx,
+                                             int32_t* count)
+{
+    __shared__ int s_cnt[kVisRounds * kWavesPerBlock];
+    __shared__ int s_base;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    uint64_t bal[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        bal[s] = __ballot(vis[s]);
+        if (lane == 0) s_cnt[s * kWavesPerBlock + wave] = __popcll(bal[s]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < kVisRounds * kWavesPerBlock; ++k) {
+            const int c = s_cnt[k];
+            s_cnt[k] = run;
+            run += c;
+        }
+        s_base = run > 0 ? atomicAdd(count, run) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        if (vis[s]) {
+            const int off = s_base + s_cnt[s * kWavesPerBlock + wave] + lanes_below(bal[s]);
+            idx[off] = (int32_t)(first + s * kBlock + threadIdx.x);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restrict__ means,
+                                                            const float* __restrict__ radius, int64_t n,
+                                                            KCamera cam, uint8_t* __restrict__ mask,
+                                                            int32_t* __restrict__ idx, int32_t* count)
+{
+    const int64_t first = (int64_t)blockIdx.x * kVisPerBlock;
+    bool vis[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        const int64_t i = first + s * kBlock + threadIdx.x;
+        bool v = false;
+        if (i < n) {
+            const float* mu = means + 3 * i;
+            v = visible_pred(mu[0], mu[1], mu[2], radius != nullptr ? radius + i : nullptr, cam);
+            if (mask != nullptr) mask[i] = (uint8_t)v;
+        }
+        vis[s] = v;
+    }
+    if (idx != nullptr) block_append(vis, first, idx, count);
+}
+
+__global__ __launch_bounds__(kBlock) void compact_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                                         int32_t* __restrict__ idx, int32_t* count)
+{
+    const int64_t first = (int64_t)blockIdx.x * kVisPerBlock;
+    bool vis[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        const int64_t i = first + s * kBlock + threadIdx.x;
+        vis[s] = i < n && mask[i] != 0;
+    }
+    block_append(vis, first, idx, count);
+}
+
+// Clears the visible count before the appends (a kernel rather than a memset
+// so the sequence can sit inside a captured graph).
+__global__ void clear_count_kernel(int32_t* count)
+{
+    if (threadIdx.x == 0) count[0] = 0;
+}
+
+hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
+                             uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream)
+{
+    if (idx != nullptr) {
+        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kWave), 0, stream, count);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
+    hipLaunchKernelGGL(visibility_kernel, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam, mask,
+                       idx, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream)
+{
+    hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kWave), 0, stream, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
+    hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, stream, mask, n, idx, count);
+    return hipGetLastError();
+}
+
+}  // namespace gs

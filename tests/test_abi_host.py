@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/gsopt.h declares, and rejects invalid arguments with
+GS_EINVAL before anything is enqueued (no call here reaches a launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsopt.h")
+
+gs = pytest.importorskip("paper_2601_16736_amd", reason="libgsopt.so not built")
+
+FAKE = 0x7F0000000000          # an aligned address that is never dereferenced
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(gs.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in gsopt.h but not exported"
+    assert set(gs.EXPORTED) == set(names)
+
+
+def test_version_and_reg_norm():
+    assert gs.version() == 1
+    for n_i in (1e6, 1089480, 404301, 999999, 10, 7, 0.5):
+        assert gs.gs_reg_norm(n_i) == oracle.reg_norm(n_i)
+
+
+def _group(**kw):
+    d = dict(param=FAKE, grad=FAKE + 4096, exp_avg=FAKE + 8192, exp_avg_sq=FAKE + 12288, lr=1e-3)
+    d.update(kw)
+    return gs.Group(**d)
+
+
+class _Fake:
+    """Stands in for a tensor: only shape and data_ptr are read."""
+
+    def __init__(self, addr, shape):
+        self._a, self.shape = addr, shape
+
+    def data_ptr(self):
+        return self._a
+
+
+def _step(groups=None, n=10, cfg=None, **kw):
+    groups = [_group(param=_Fake(FAKE, (n, 3)))] if groups is None else groups
+    cfg = cfg or gs.StepConfig(schedule=gs.GS_SCHED_DENSE)
+    with pytest.raises(gs.GsError) as e:
+        gs.adamw_gs_step(groups, n, kw.pop("t", FAKE + 65536), cfg, stream=0, **kw)
+    return e.value
+
+
+@pytest.mark.parametrize("cfg", [
+    gs.StepConfig(beta1=1.0, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(beta1=-0.1, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(beta2=1.0, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(eps=0.0, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(eps=1e-60, schedule=gs.GS_SCHED_DENSE),      # rounds to 0 in FP32
+    gs.StepConfig(eps=float("nan"), schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(moment_dtype=5, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(rsr_enable=True, rsr_alpha1=1.0, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(rsr_enable=True, rsr_alpha2=-0.5, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(rsr_enable=True, rsr_ratio=1.5, schedule=gs.GS_SCHED_DENSE),
+    gs.StepConfig(schedule=9),
+    gs.StepConfig(schedule=gs.GS_SCHED_COMPACTED),             # no vis_idx
+    gs.StepConfig(schedule=gs.GS_SCHED_MASKED),                # no mask
+    gs.StepConfig(schedule=gs.GS_SCHED_DENSE, unit=100),       # unknown unit
+    gs.StepConfig(schedule=gs.GS_SCHED_DENSE, iteration=-1),
+])
+def test_step_rejects_bad_config(cfg):
+    e = _step(cfg=cfg)
+    assert e.status == gs.GS_EINVAL, str(e)
+
+
+def test_step_rejects_bad_groups_and_sizes():
+    assert _step(n=-1).status == gs.GS_EINVAL
+    assert _step(n=2**31).status == gs.GS_EINVAL
+    assert _step(groups=[]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)))] * 9).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE + 2, (10, 3)))]).status == gs.GS_EINVAL   # misaligned
+    assert _step(groups=[_group(param=_Fake(0, (10, 3)))]).status == gs.GS_EINVAL          # NULL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), dar_kind=7)]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), reg_mode=3)]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), lr=float("inf"))]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), dar_lambda=-1.0)]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), dar_kind=1)],
+                 cfg=gs.StepConfig(reg_norm=0.0, schedule=gs.GS_SCHED_DENSE)).status == gs.GS_EINVAL
+    assert _step(t=0).status == gs.GS_EINVAL                                             # step_count NULL
+    e = _step(n=-5)
+    assert "n = -5" in str(e) and gs.last_error() in str(e)
+
+
+def test_visibility_rejects_bad_arguments():
+    cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
+    means = _Fake(FAKE, (10, 3))
+    cases = [
+        dict(mask=None, vis_idx=None),                          # no output
+        dict(mask=FAKE + 4096, vis_idx=FAKE + 8192),            # idx without count
+        dict(mask=FAKE + 4097),                                 # fine: mask is bytes -> next case
+    ]
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(means, cam, stream=0, **cases[0])
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(means, cam, stream=0, **cases[1])
+    bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 0, 1000)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(means, bad, mask=FAKE + 4096, stream=0)
+    bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000, z_near=5, z_far=5)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(means, bad, mask=FAKE + 4096, stream=0)
+    bad = gs.Camera([float("nan")] + [0] * 11, 866.0, 866.0, 500, 500, 1000, 1000)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(means, bad, mask=FAKE + 4096, stream=0)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility(_Fake(FAKE + 1, (10, 3)), cam, mask=FAKE + 4096, stream=0)
+    with pytest.raises(gs.GsError):
+        gs.gs_compact(_Fake(FAKE, (10,)), FAKE + 4096, None, stream=0)
+
+
+def test_tune_rejects_bad_arguments():
+    for args in ((0, [3], 0.3), (100, [], 0.3), (100, [3], 0.0), (100, [3], 1.5), (100, [0], 0.3)):
+        with pytest.raises(gs.GsError):
+            gs.gs_tune(*args)

@@ -1,0 +1,351 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: visibility masks and index sets bit-exact; step counts exact; rows the
+step may not touch bit-identical; FP32 attributes within 1e-6 (unit-floor
+relative error) of the oracle, FP32 moments within 1e-6 (RMS floor), BF16
+moments within one bf16 ulp.  Sizes span several wave units and end in a
+ragged tail; the full-size cases use the benchmark's launch configuration.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+gs = pytest.importorskip("paper_2601_16736_amd")
+from _gpu_util import (DEV, compare, make_state, oracle_config, oracle_groups, rsr_sampled_mask,  # noqa: E402
+                       set_grads, theta_err)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def _cams(n_cams=200):
+    return synth.camera_rig(n_cams=n_cams)
+
+
+def _gcam(c, **kw):
+    return gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, kw.get("z_near", c.z_near),
+                     kw.get("z_far", c.z_far), kw.get("r_min", 0.0))
+
+
+def _ocam(c, **kw):
+    return oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, kw.get("z_near", c.z_near),
+                         kw.get("z_far", c.z_far), kw.get("r_min", 0.0))
+
+
+# ---------------------------------------------------------------- visibility
+def _boundary_means(n, seed):
+    """Uniform means plus means placed on the near/far planes and image edges."""
+    r = synth.rng(seed, 50)
+    mu = r.uniform(-10, 10, (n, 3)).astype(np.float32)
+    k = n // 10
+    # points exactly on the camera-space planes of the axis camera used below
+    mu[:k, 2] = np.float32(17.5 - 15.0)
+    mu[k:2 * k, 2] = np.float32(0.2 - 15.0)
+    return mu
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 1025, 100_003])
+@pytest.mark.parametrize("with_radius", [False, True])
+def test_visibility_bit_exact(n, with_radius):
+    means = _boundary_means(n, 1)
+    radius = (synth.rng(2, 51).random(n) * 0.5).astype(np.float32) if with_radius else None
+    cams = _cams()
+    axis = synth.CameraSpec(np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 15]], np.float32),
+                            cams[0].fx, cams[0].fy, 500.0, 500.0, 1000, 1000, 0.2, 17.5)
+    d_means = torch.from_numpy(means).to(DEV)
+    d_rad = torch.from_numpy(radius).to(DEV) if with_radius else None
+    mask = torch.full((max(n, 1),), 7, dtype=torch.uint8, device=DEV)
+    idx = torch.full((max(n, 1),), -1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), 12345, dtype=torch.int32, device=DEV)
+    for c in [axis, cams[0], cams[57], cams[199]]:
+        kw = {"r_min": 0.5} if with_radius else {}
+        gs.gs_visibility(d_means, _gcam(c, **kw), mask=mask[:n] if n else mask, vis_idx=idx, vis_count=cnt,
+                         radius=d_rad)
+        torch.cuda.synchronize()
+        ref = oracle.visibility(means, _ocam(c, **kw), radius)
+        np.testing.assert_array_equal(mask.cpu().numpy()[:n], ref)
+        k = int(cnt.item())
+        assert k == int(ref.sum())
+        got = idx.cpu().numpy()[:k]
+        np.testing.assert_array_equal(np.sort(got), np.flatnonzero(ref))
+
+
+def test_visibility_mask_only_and_index_only():
+    n = 40_000
+    means = _boundary_means(n, 3)
+    c = _cams()[11]
+    d_means = torch.from_numpy(means).to(DEV)
+    ref = oracle.visibility(means, _ocam(c))
+    mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.gs_visibility(d_means, _gcam(c), mask=mask)
+    idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    gs.gs_visibility(d_means, _gcam(c), vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(mask.cpu().numpy(), ref)
+    np.testing.assert_array_equal(np.sort(idx.cpu().numpy()[:int(cnt.item())]), np.flatnonzero(ref))
+
+
+@pytest.mark.parametrize("p", [0.0, 0.02, 0.3, 1.0])
+@pytest.mark.parametrize("n", [1, 1000, 77_777])
+def test_compact_matches_nonzero(p, n):
+    mask = (synth.rng(4, 52).random(n) < p).astype(np.uint8) * np.uint8(3)   # any nonzero byte counts
+    idx = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), 999, dtype=torch.int32, device=DEV)
+    gs.gs_compact(torch.from_numpy(mask).to(DEV), idx, cnt)
+    torch.cuda.synchronize()
+    k = int(cnt.item())
+    assert k == int((mask != 0).sum())
+    np.testing.assert_array_equal(np.sort(idx.cpu().numpy()[:k]), oracle.compact((mask != 0).astype(np.uint8)))
+
+
+# ---------------------------------------------------------------- one step
+SCHEDS = [(gs.GS_SCHED_COMPACTED, u) for u in (64, 128, 256, 512)] + \
+         [(gs.GS_SCHED_MASKED, u) for u in (128, 256, 512)] + [(gs.GS_SCHED_DENSE, u) for u in (256, 512)]
+LAYOUTS = {"59": synth.GROUPS_59, "60split": synth.GROUPS_60_SPLIT}
+MOMENTS = {"f32": (False, False), "bf16_rne": (True, False), "bf16_sr": (True, True)}
+
+
+def _one_step(n, spec, sched, unit, bf16, sr, rsr, seed, p_vis=0.3, iteration=7, dar_lambda=None,
+              reg_mode=0, nonzero_state=True, dar_clip=10.0):
+    st = make_state(gs, n, spec, seed, bf16=bf16, dar_lambda=dar_lambda, reg_mode=reg_mode,
+                    nonzero_state=nonzero_state, dar_clip=dar_clip)
+    if sched == gs.GS_SCHED_DENSE:
+        mask = np.ones(n, np.uint8)
+    else:
+        mask = synth.bernoulli_mask(n, p_vis, seed, iteration)
+    set_grads(st, mask, seed, iteration, poison_invisible=True)
+    d_mask = torch.from_numpy(mask).to(DEV)
+    idx = torch.zeros(max(n, 1), dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    if n:
+        gs.gs_compact(d_mask, idx, cnt)
+    cfg = gs.StepConfig(iteration=iteration, seed=seed * 31 + 5, moment_dtype=int(bf16), stochastic_round=sr,
+                        rsr_enable=rsr, rsr_ratio=0.3, schedule=sched, unit=unit)
+    torch.cuda.synchronize()
+    before = st.host()
+    gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask, vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    after = st.host()
+    og = oracle_groups(before, spec, st.groups)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, n, None if sched == gs.GS_SCHED_DENSE else mask, t_ref, oracle_config(cfg))
+    touched = mask.astype(bool)
+    if rsr:
+        touched = touched | rsr_sampled_mask(n, cfg.seed, cfg.iteration, cfg.rsr_ratio)
+    return compare(after, before, og, spec, t_ref, touched, bf16, label=f"n={n} sched={sched}/{unit}")
+
+
+@pytest.mark.parametrize("sched,unit", SCHEDS)
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+@pytest.mark.parametrize("moments", list(MOMENTS))
+@pytest.mark.parametrize("rsr", [False, True])
+def test_step_parity_small(sched, unit, layout, moments, rsr):
+    bf16, sr = MOMENTS[moments]
+    for n in (257, 3001):
+        _one_step(n, LAYOUTS[layout], sched, unit, bf16, sr, rsr, seed=n + unit)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65])
+def test_step_tiny_sizes(n):
+    for sched, unit in ((gs.GS_SCHED_COMPACTED, 64), (gs.GS_SCHED_MASKED, 128), (gs.GS_SCHED_DENSE, 256)):
+        _one_step(n, synth.GROUPS_59, sched, unit, False, False, True, seed=3 + n, p_vis=0.5)
+
+
+@pytest.mark.parametrize("reg_mode", [gs.GS_REG_ADAPTIVE, gs.GS_REG_CONSTANT, gs.GS_REG_CONSTANT_CLIPPED])
+@pytest.mark.parametrize("lam", [1e-3, 10.0, 1e4])
+def test_step_regulariser_modes_and_strengths(reg_mode, lam):
+    # large lambda makes the DAR term comparable to or above C, so the clamp,
+    # the 1/d preconditioning and the pre-update theta all matter
+    _one_step(4099, synth.GROUPS_59, gs.GS_SCHED_COMPACTED, 128, False, False, True, seed=11,
+              dar_lambda=lam, reg_mode=reg_mode, dar_clip=0.5)
+
+
+def test_step_zero_state_and_zero_gradients():
+    """Fresh primitives (m = v = 0, t = 0) with some zero gradients: d = eps,
+    so the DAR term clamps at C and theta moves by exactly lr * C there."""
+    n = 2000
+    spec = synth.GROUPS_59
+    st = make_state(gs, n, spec, 21, nonzero_state=False)
+    mask = synth.bernoulli_mask(n, 0.5, 21, 0)
+    set_grads(st, mask, 21, 0)
+    for g in st.groups:
+        g.grad[: n // 2] = 0.0
+    d_mask = torch.from_numpy(mask).to(DEV)
+    cfg = gs.StepConfig(iteration=0, schedule=gs.GS_SCHED_MASKED)
+    before = st.host()
+    gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask)
+    torch.cuda.synchronize()
+    after = st.host()
+    og = oracle_groups(before, spec, st.groups)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, n, mask, t_ref, oracle_config(cfg))
+    compare(after, before, og, spec, t_ref, mask.astype(bool), False, "zero-state")
+    op = after["opacity"]["param"][: n // 2, 0]
+    vis = mask[: n // 2] == 1
+    np.testing.assert_array_equal(op[vis], (before["opacity"]["param"][: n // 2, 0][vis] - np.float32(0.05) *
+                                            np.float32(10.0)))
+
+
+def test_schedules_give_identical_bits():
+    """Rows are independent, so every schedule, unit size and index order must
+    produce the same bits (same arithmetic per element)."""
+    n = 20_000
+    spec = synth.GROUPS_60_SPLIT
+    mask = synth.bernoulli_mask(n, 0.25, 5, 3)
+    results = []
+    for k, (sched, unit, shuffle) in enumerate([(gs.GS_SCHED_COMPACTED, 64, False), (gs.GS_SCHED_COMPACTED, 512, True),
+                                                (gs.GS_SCHED_MASKED, 128, False), (gs.GS_SCHED_MASKED, 512, False)]):
+        st = make_state(gs, n, spec, 5)
+        set_grads(st, mask, 5, 3)
+        d_mask = torch.from_numpy(mask).to(DEV)
+        vis = np.flatnonzero(mask).astype(np.int32)
+        if shuffle:
+            vis = synth.rng(9).permutation(vis).astype(np.int32)
+        idx = torch.from_numpy(vis).to(DEV)
+        cnt = torch.tensor([len(vis)], dtype=torch.int32, device=DEV)
+        cfg = gs.StepConfig(iteration=3, seed=9, schedule=sched, unit=unit, rsr_enable=True, rsr_ratio=0.2)
+        gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask, vis_idx=idx, vis_count=cnt)
+        torch.cuda.synchronize()
+        results.append(st.host())
+    for other in results[1:]:
+        for name, *_ in spec:
+            for key in ("param", "m", "v"):
+                np.testing.assert_array_equal(other[name][key], results[0][name][key])
+        np.testing.assert_array_equal(other["_t"], results[0]["_t"])
+
+
+def test_dense_schedule_is_synchronous_adam():
+    """V = 1 everywhere reduces to Adam + DAR on every primitive."""
+    _one_step(5000, synth.GROUPS_59, gs.GS_SCHED_DENSE, 512, False, False, False, seed=77)
+
+
+def test_auto_schedule_and_tuner():
+    n = 50_000
+    s, u = gs.gs_tune(n, [d for _, d, _, _ in synth.GROUPS_59], 0.3)
+    assert s in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED) and u in (64, 128, 256, 512)
+    st = make_state(gs, n, synth.GROUPS_59, 8)
+    mask = synth.bernoulli_mask(n, 0.3, 8, 1)
+    set_grads(st, mask, 8, 1)
+    d_mask = torch.from_numpy(mask).to(DEV)
+    idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    gs.gs_compact(d_mask, idx, cnt)
+    cfg = gs.StepConfig(iteration=1, schedule=gs.GS_SCHED_AUTO, visible_hint=0.3)
+    before = st.host()
+    gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask, vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    og = oracle_groups(before, synth.GROUPS_59, st.groups)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, n, mask, t_ref, oracle_config(cfg))
+    compare(st.host(), before, og, synth.GROUPS_59, t_ref, mask.astype(bool), False, "auto")
+    gs.gs_tune_clear()
+
+
+# ---------------------------------------------------------------- trajectories
+def test_config1_trajectory_20_steps():
+    """100k primitives, 59 floats each, Bernoulli(0.3) visibility and N(0,1e-3)
+    gradients per step, paper DAR settings; RSR every 5 steps (p = 0.05).
+    GPU and oracle run free from the same start; attributes must stay within
+    1e-6 after 20 steps, step counts exact."""
+    n, steps = 100_000, 20
+    spec = synth.GROUPS_59
+    scene = synth.scene_uniform(n, seed=0, groups=spec)
+    st = make_state(gs, n, spec, 0, nonzero_state=False)
+    for (name, *_), g in zip(spec, st.groups):
+        g.param.copy_(torch.from_numpy(scene.params[name]))
+    og = oracle_groups(st.host(), spec, st.groups)
+    t_ref = np.zeros(n, np.int32)
+    idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    for s in range(steps):
+        mask = synth.bernoulli_mask(n, 0.3, 0, s)
+        gr = synth.grads(n, spec, mask, 0, s)
+        for (name, *_), g, o in zip(spec, st.groups, og):
+            g.grad.copy_(torch.from_numpy(gr[name]))
+            o.grad[:] = gr[name]
+        d_mask = torch.from_numpy(mask).to(DEV)
+        gs.gs_compact(d_mask, idx, cnt)
+        cfg = gs.StepConfig(iteration=s, seed=0, rsr_enable=(s % 5 == 4), rsr_ratio=0.05,
+                            schedule=gs.GS_SCHED_COMPACTED, unit=128)
+        gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask, vis_idx=idx, vis_count=cnt)
+        oracle.adamw_gs_step(og, n, mask, t_ref, oracle_config(cfg))
+    torch.cuda.synchronize()
+    after = st.host()
+    np.testing.assert_array_equal(after["_t"], t_ref)
+    for (name, *_), o in zip(spec, og):
+        e = theta_err(after[name]["param"], o.param)
+        assert e <= 1e-6, f"{name}: theta drift {e:.3e} after {steps} steps"
+
+
+# ---------------------------------------------------------------- full size
+def test_full_size_scene_sampled_rows():
+    """3M-primitive scene (means U[-10,10]^3, rig camera, z_far 17.5): the
+    whole mask bit-exact; one step in the benchmark's launch configuration
+    with RSR on; sampled visible, invisible and RSR-sampled rows against the
+    oracle one by one; step counts and untouched rows over all 3M."""
+    import bench
+    n = 3_000_000
+    spec = synth.GROUPS_59
+    scene = synth.scene_uniform(n, seed=0, groups=spec)
+    c = _cams()[37]
+    means_h = scene.params["means"]
+    st = make_state(gs, n, spec, 12)
+    for (name, *_), g in zip(spec, st.groups):
+        g.param.copy_(torch.from_numpy(scene.params[name]))
+    mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    gs.gs_visibility(st.groups[0].param, _gcam(c), mask=mask, vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    ref_mask = oracle.visibility(means_h, _ocam(c))
+    m = mask.cpu().numpy()
+    np.testing.assert_array_equal(m, ref_mask)
+    frac = m.mean()
+    assert 0.05 < frac < 0.40
+    set_grads(st, m, 12, 100, poison_invisible=False)
+    cfg = gs.StepConfig(iteration=100, seed=0, rsr_enable=True, rsr_ratio=0.05, **bench.STEP_LAUNCH)
+    r = synth.rng(13)
+    vis_rows = r.choice(np.flatnonzero(m), 3000, replace=False)
+    inv_rows = r.choice(np.flatnonzero(m == 0), 3000, replace=False)
+    sampled_all = rsr_sampled_mask(n, cfg.seed, cfg.iteration, cfg.rsr_ratio)
+    smp_rows = r.choice(np.flatnonzero(sampled_all), 2000, replace=False)
+    rows = np.unique(np.concatenate([vis_rows, inv_rows, smp_rows])).astype(np.int64)
+    rows_t = torch.from_numpy(rows).to(DEV)
+
+    def take(st_):
+        out = {}
+        for (name, *_), g in zip(spec, st_.groups):
+            out[name] = {"param": g.param[rows_t].cpu().numpy(), "grad": g.grad[rows_t].cpu().numpy(),
+                         "m": g.exp_avg[rows_t].cpu().numpy().astype(np.float64),
+                         "v": g.exp_avg_sq[rows_t].cpu().numpy().astype(np.float64)}
+        out["_t"] = st_.t[rows_t].cpu().numpy()
+        return out
+
+    before = take(st)
+    t_before_all = st.t.clone()
+    untouched = torch.from_numpy(~(ref_mask.astype(bool) | sampled_all)).to(DEV)
+    snap = [g.param[untouched].clone() for g in st.groups[:2]]
+    gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=mask, vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    after = take(st)
+    og = oracle_groups(before, spec, st.groups)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, len(rows), ref_mask[rows].copy(), t_ref, oracle_config(cfg), ids=rows)
+    touched = ref_mask[rows].astype(bool) | sampled_all[rows]
+    compare(after, before, og, spec, t_ref, touched, False, "3M sampled")
+    dt = (st.t - t_before_all).cpu().numpy()
+    np.testing.assert_array_equal(dt, m.astype(np.int32))
+    for s0, g in zip(snap, st.groups[:2]):
+        assert torch.equal(g.param[untouched], s0)
