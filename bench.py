@@ -37,7 +37,7 @@ import numpy as np  # noqa: E402
 
 # Launch configuration of the fused step in the benchmark (the full-size
 # parity test runs the same one).
-STEP_LAUNCH = {"schedule": 1, "unit": 128}          # compacted schedule, 128 rows per wave
+STEP_LAUNCH = {"schedule": 1, "unit": 64}           # compacted schedule, 64 rows per wave
 
 N_PRIMS = 3_000_000
 HBM_PEAK_GBS = 8000.0
@@ -101,6 +101,23 @@ def cpu_baseline(scene, cams, order, budget_s: float = 12.0, sample_n: int = 300
                       f"{elapsed:.1f} s, 1 thread"}
 
 
+def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "copy_GBps_rw": 2 * nbytes / dt / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +125,11 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
     args = ap.parse_args(argv)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the AdamW-GS step has no cross-GPU exchange to measure "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)

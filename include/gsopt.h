@@ -290,6 +290,37 @@ gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, float visibl
 /* Removes every tuner entry. */
 void gs_tune_clear(void);
 
+/* ------------------------------------------------------------------------
+ * Spatial layout.  The step touches every attribute row of each visible
+ * primitive; when the primitives a view sees are scattered over the index
+ * range, each small row drags a whole 128-byte line (and a DRAM page) with it.
+ * Ordering the primitives along a Z-order (Morton) curve of their means puts
+ * what one view sees into long contiguous index runs.  These two calls compute
+ * such an order and apply it to any per-primitive array; they are meant for
+ * scene set-up and for the moments when the primitive set changes anyway
+ * (densification), not for every step.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace gs_spatial_order needs for n primitives. */
+size_t gs_spatial_order_workspace_size(int64_t n);
+
+/*
+ * perm [n] int32 out: primitive indices sorted by the 30-bit Morton code of
+ * their mean (10 bits per axis over the bounding box of the means; NaN
+ * coordinates take part as the box minimum), ties in index order.
+ * means [n][3] FP32.  workspace: gs_spatial_order_workspace_size(n) bytes,
+ * 256-byte aligned.
+ */
+gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * dst row i = src row perm[i] for n rows of row_bytes bytes (dst != src).
+ * Entries of perm outside [0, n) leave their dst row untouched.
+ */
+gs_status gs_gather_rows(const void* src, void* dst, const int32_t* perm, int64_t n,
+                         int64_t row_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,10 +104,17 @@ _lib.gs_tune.argtypes = [_i64, ctypes.POINTER(_i32), _i32, ctypes.c_float, _i32,
                          ctypes.POINTER(_i32)]
 _lib.gs_tune_clear.restype = None
 _lib.gs_tune_clear.argtypes = []
+_lib.gs_spatial_order_workspace_size.restype = _sz
+_lib.gs_spatial_order_workspace_size.argtypes = [_i64]
+_lib.gs_spatial_order.restype = _i32
+_lib.gs_spatial_order.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
+_lib.gs_gather_rows.restype = _i32
+_lib.gs_gather_rows.argtypes = [_vp, _vp, _vp, _i64, _i64, _vp]
 
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_compact", "adamw_gs_step",
             "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
-            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear"]
+            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
+            "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows"]
 
 
 def _check(status: int) -> None:
@@ -351,3 +358,32 @@ def gs_tune(n: int, dims: Sequence[int], visible_fraction: float, moment_dtype: 
 
 def gs_tune_clear() -> None:
     _lib.gs_tune_clear()
+
+
+# --------------------------------------------------------------------------
+def gs_spatial_order_workspace_size(n: int) -> int:
+    return int(_lib.gs_spatial_order_workspace_size(int(n)))
+
+
+def gs_spatial_order(means, perm, workspace, stream=None) -> None:
+    """perm <- primitive indices in Morton order of their means."""
+    ws_bytes = int(workspace.numel() * workspace.element_size())
+    _check(_lib.gs_spatial_order(_ptr(means), int(means.shape[0]), _ptr(perm), _ptr(workspace), ws_bytes,
+                                 _stream(stream)))
+
+
+def gs_gather_rows(src, dst, perm, stream=None) -> None:
+    """dst[i] = src[perm[i]] row by row (rows = leading dimension)."""
+    n = int(src.shape[0])
+    row_bytes = int(src[0].numel() * src.element_size()) if n else 1
+    _check(_lib.gs_gather_rows(_ptr(src), _ptr(dst), _ptr(perm), n, row_bytes, _stream(stream)))
+
+
+def apply_spatial_order(tensors, perm, stream=None):
+    """Returns copies of the given per-primitive tensors permuted by perm."""
+    out = []
+    for t in tensors:
+        d = t.new_empty(t.shape)
+        gs_gather_rows(t.contiguous(), d, perm, stream)
+        out.append(d)
+    return out

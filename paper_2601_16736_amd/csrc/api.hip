@@ -198,9 +198,10 @@ gs_status resolve_schedule(int requested, int unit, float hint, int64_t n, int n
     }
     (void)n_groups;
     (void)dims;
-    if (sched == kSchedCompacted && (idx == nullptr || count == nullptr))
+    if (n > 0 && sched == kSchedCompacted && (idx == nullptr || count == nullptr))
         return fail(GS_EINVAL, "%scompacted schedule needs vis_idx and vis_count", prefix);
-    if (sched == kSchedMasked && mask == nullptr) return fail(GS_EINVAL, "%smasked schedule needs visible", prefix);
+    if (n > 0 && sched == kSchedMasked && mask == nullptr)
+        return fail(GS_EINVAL, "%smasked schedule needs visible", prefix);
     if (sched != kSchedCompacted && sched != kSchedMasked && sched != kSchedDense)
         return fail(GS_EINVAL, "%sunknown schedule %d", prefix, requested);
     if (unit == 0) unit = default_unit(sched);
@@ -296,7 +297,7 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     st = resolve_schedule(cfg->schedule, cfg->unit, cfg->visible_hint, n, n_groups, dims, cfg->moment_dtype, visible,
                           vis_idx, vis_count, &sched, &unit, "");
     if (st != GS_OK) return st;
-    if (cfg->rsr_enable && h.rsr_thr > 0 && sched != kSchedDense && visible == nullptr)
+    if (n > 0 && cfg->rsr_enable && h.rsr_thr > 0 && sched != kSchedDense && visible == nullptr)
         return fail(GS_EINVAL, "RSR with a sparse schedule needs the visibility mask (to rescale invisible rows)");
     s.sched = sched;
     s.unit = unit;

@@ -60,52 +60,85 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 }
 
 // ---------------------------------------------------------------- vector access
+// Attribute and moment streams are touched once per step, so accesses may be
+// marked non-temporal: 0 = none, 1 = 8/16-byte accesses only, 2 = all.
+#ifndef GS_STEP_NT
+#define GS_STEP_NT 1
+#endif
+// 1: hardware square root and reciprocal (about 1 ulp each) in the update
+// instead of the correctly rounded sequences
+#ifndef GS_FAST_RCP
+#define GS_FAST_RCP 0
+#endif
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T, bool NT> __device__ __forceinline__ T ld(const T* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T, bool NT> __device__ __forceinline__ void st(T* p, T x)
+{
+    if constexpr (NT) __builtin_nontemporal_store(x, p);
+    else *p = x;
+}
+
 template <int V> __device__ __forceinline__ void load_f(const float* p, float* x)
 {
     if constexpr (V == 4) {
-        const float4 t = *reinterpret_cast<const float4*>(p);
+        const f32x4 t = ld<f32x4, (GS_STEP_NT >= 1)>(reinterpret_cast<const f32x4*>(p));
         x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
     } else if constexpr (V == 2) {
-        const float2 t = *reinterpret_cast<const float2*>(p);
+        const f32x2 t = ld<f32x2, (GS_STEP_NT >= 1)>(reinterpret_cast<const f32x2*>(p));
         x[0] = t.x; x[1] = t.y;
     } else {
-        x[0] = *p;
+        x[0] = ld<float, (GS_STEP_NT >= 2)>(p);
     }
 }
 
 template <int V> __device__ __forceinline__ void store_f(float* p, const float* x)
 {
     if constexpr (V == 4) {
-        *reinterpret_cast<float4*>(p) = make_float4(x[0], x[1], x[2], x[3]);
+        f32x4 t;
+        t.x = x[0]; t.y = x[1]; t.z = x[2]; t.w = x[3];
+        st<f32x4, (GS_STEP_NT >= 1)>(reinterpret_cast<f32x4*>(p), t);
     } else if constexpr (V == 2) {
-        *reinterpret_cast<float2*>(p) = make_float2(x[0], x[1]);
+        f32x2 t;
+        t.x = x[0]; t.y = x[1];
+        st<f32x2, (GS_STEP_NT >= 1)>(reinterpret_cast<f32x2*>(p), t);
     } else {
-        *p = x[0];
+        st<float, (GS_STEP_NT >= 2)>(p, x[0]);
     }
 }
 
 template <int V> __device__ __forceinline__ void load_h(const uint16_t* p, float* x)
 {
     if constexpr (V == 4) {
-        const uint2 t = *reinterpret_cast<const uint2*>(p);
+        const u32x2 t = ld<u32x2, (GS_STEP_NT >= 1)>(reinterpret_cast<const u32x2*>(p));
         x[0] = bf16_to_f32(t.x & 0xFFFFu); x[1] = bf16_to_f32(t.x >> 16);
         x[2] = bf16_to_f32(t.y & 0xFFFFu); x[3] = bf16_to_f32(t.y >> 16);
     } else if constexpr (V == 2) {
-        const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+        const uint32_t t = ld<uint32_t, (GS_STEP_NT >= 2)>(reinterpret_cast<const uint32_t*>(p));
         x[0] = bf16_to_f32(t & 0xFFFFu); x[1] = bf16_to_f32(t >> 16);
     } else {
-        x[0] = bf16_to_f32(*p);
+        x[0] = bf16_to_f32(ld<uint16_t, (GS_STEP_NT >= 2)>(p));
     }
 }
 
 template <int V> __device__ __forceinline__ void store_h(uint16_t* p, const uint32_t* h)
 {
     if constexpr (V == 4) {
-        *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        u32x2 t;
+        t.x = h[0] | (h[1] << 16); t.y = h[2] | (h[3] << 16);
+        st<u32x2, (GS_STEP_NT >= 1)>(reinterpret_cast<u32x2*>(p), t);
     } else if constexpr (V == 2) {
-        *reinterpret_cast<uint32_t*>(p) = h[0] | (h[1] << 16);
+        st<uint32_t, (GS_STEP_NT >= 2)>(reinterpret_cast<uint32_t*>(p), h[0] | (h[1] << 16));
     } else {
-        *p = (uint16_t)h[0];
+        st<uint16_t, (GS_STEP_NT >= 2)>(p, (uint16_t)h[0]);
     }
 }
 
@@ -162,8 +195,10 @@ __device__ __forceinline__ float reg_term(int kind, int mode, float scale, float
     return fminf(scale * R, clip);
 }
 
-// One group's read-modify-write pass over the wave's staged rows.
-template <bool BF16, int V>
+// One group's read-modify-write pass over the wave's staged rows.  Each
+// lane takes U (row, chunk) items per trip and issues all their loads before
+// any store, so a wave keeps U x 4 vector loads in flight.
+template <bool BF16, int V, int U>
 __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int nrows,
                                            const int* s_row, const float* s_rb1, const float* s_rsb2,
                                            int lane, uint64_t sr_s2)
@@ -176,37 +211,57 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
     const int dr = kWave / cpr;
     const int dc = kWave - dr * cpr;
     const bool dar = G.dar_kind != GS_DAR_NONE;
-    for (int k = lane; k < items; k += kWave) {
-        const int raw = s_row[r];
-        const int prim = raw & 0x7FFFFFFF;
-        // a row in this iteration's Re-State sample decays by alpha before the
-        // moment update: beta*(alpha*m) folded into (beta*alpha)*m
-        const float c1 = raw < 0 ? H.c1_rsr : H.beta1;
-        const float c2 = raw < 0 ? H.c2_rsr : H.beta2;
-        const float rb1 = s_rb1[r];
-        const float rsb2 = s_rsb2[r];
-        const int64_t e = (int64_t)prim * dim + c * V;
-        float th[V], g[V], m[V], v[V];
-        load_f<V>(G.param + e, th);
-        load_f<V>(G.grad + e, g);
-        load_moment<BF16, V>(G.m, e, m);
-        load_moment<BF16, V>(G.v, e, v);
+    for (int k0 = lane; k0 < items; k0 += U * kWave) {
+        int64_t e[U];
+        float c1[U], c2[U], rb1[U], rsb2[U];
+        bool ok[U];
 #pragma unroll
-        for (int q = 0; q < V; ++q) {
-            const float mm = c1 * m[q] + H.omb1 * g[q];
-            const float vv = c2 * v[q] + H.omb2 * (g[q] * g[q]);
-            const float d = __fsqrt_rn(vv) * rsb2 + H.eps;       // sqrt(v / b2) + eps
-            float u = (mm * rb1) / d;                             // (m / b1) / d
-            if (dar) u += reg_term(G.dar_kind, G.reg_mode, G.dar_scale, G.dar_clip, th[q], d);
-            th[q] = th[q] - G.lr * u;
-            m[q] = mm;
-            v[q] = vv;
+        for (int u = 0; u < U; ++u) {
+            ok[u] = k0 + u * kWave < items;
+            const int raw = ok[u] ? s_row[r] : 0;
+            // a row in this iteration's Re-State sample decays by alpha before
+            // the moment update: beta*(alpha*m) folded into (beta*alpha)*m
+            c1[u] = raw < 0 ? H.c1_rsr : H.beta1;
+            c2[u] = raw < 0 ? H.c2_rsr : H.beta2;
+            rb1[u] = ok[u] ? s_rb1[r] : 1.0f;
+            rsb2[u] = ok[u] ? s_rsb2[r] : 1.0f;
+            e[u] = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
+            r += dr;
+            c += dc;
+            if (c >= cpr) { c -= cpr; ++r; }
         }
-        store_f<V>(G.param + e, th);
-        store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
-        r += dr;
-        c += dc;
-        if (c >= cpr) { c -= cpr; ++r; }
+        float th[U][V], g[U][V], m[U][V], v[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (ok[u]) {
+                load_f<V>(G.param + e[u], th[u]);
+                load_f<V>(G.grad + e[u], g[u]);
+                load_moment<BF16, V>(G.m, e[u], m[u]);
+                load_moment<BF16, V>(G.v, e[u], v[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const float mm = c1[u] * m[u][q] + H.omb1 * g[u][q];
+                const float vv = c2[u] * v[u][q] + H.omb2 * (g[u][q] * g[u][q]);
+#if GS_FAST_RCP
+                const float d = __builtin_amdgcn_sqrtf(vv) * rsb2[u] + H.eps;
+                float uu = (mm * rb1[u]) * __builtin_amdgcn_rcpf(d);
+#else
+                const float d = __fsqrt_rn(vv) * rsb2[u] + H.eps;       // sqrt(v / b2) + eps
+                float uu = (mm * rb1[u]) / d;                            // (m / b1) / d
+#endif
+                if (dar) uu += reg_term(G.dar_kind, G.reg_mode, G.dar_scale, G.dar_clip, th[u][q], d);
+                th[u][q] = th[u][q] - G.lr * uu;
+                m[u][q] = mm;
+                v[u][q] = vv;
+            }
+            store_f<V>(G.param + e[u], th[u]);
+            store_moments<BF16, V>(G.m, G.v, e[u], m[u], v[u], H.sr != 0, sr_s2);
+        }
     }
 }
 
@@ -333,16 +388,21 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
 }
 
 // Every group's pass over the staged rows.
+#ifndef GS_STEP_UNROLL
+#define GS_STEP_UNROLL 2
+#endif
+
 template <bool BF16>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, int nrows, const int* s_row,
                                                 const float* s_rb1, const float* s_rsb2, int lane)
 {
+    constexpr int U = GS_STEP_UNROLL;
     for (int gi = 0; gi < S.n_groups; ++gi) {
         const KGroup& G = S.g[gi];
         const uint64_t s2 = BF16 ? d_splitmix(G.sr_s1, (uint64_t)H.iteration + 1) : 0;
-        if (G.vec == 4) step_group<BF16, 4>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
-        else if (G.vec == 2) step_group<BF16, 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
-        else step_group<BF16, 1>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        if (G.vec == 4) step_group<BF16, 4, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        else if (G.vec == 2) step_group<BF16, 2, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        else step_group<BF16, 1, U * 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
     }
 }
 

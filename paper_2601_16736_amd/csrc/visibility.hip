@@ -1,15 +1,16 @@
 // Per-view visibility (frustum/radius cull of the projected means) and
 // compaction of the visible indices (gfx950).
 //
-// Each block of 256 threads covers 1024 consecutive primitives in four
+// Each block of 256 threads covers 4096 consecutive primitives in sixteen
 // rounds.  Per round a wave ballots its 64 predicates; the block adds up its
-// 16 wave counts and reserves one contiguous range of the index list with a
-// single atomic, so the list holds ascending runs of up to 1024 primitives.
+// 64 (round, wave) counts and reserves one contiguous range of the index list
+// with a single atomic, so the list holds ascending runs of up to 4096
+// primitives and the one shared counter sees n/4096 atomics.
 #include "device_common.h"
 
 namespace gs {
 
-constexpr int kVisRounds = 4;
+constexpr int kVisRounds = 16;
 constexpr int kVisPerBlock = kBlock * kVisRounds;
 
 // The FP32 predicate, one rounding per operation in the stated order (no
@@ -51,14 +52,19 @@ __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int6
         if (lane == 0) s_cnt[s * kWavesPerBlock + wave] = __popcll(bal[s]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int k = 0; k < kVisRounds * kWavesPerBlock; ++k) {
-            const int c = s_cnt[k];
-            s_cnt[k] = run;
-            run += c;
+    if (threadIdx.x < kWave) {
+        // exclusive prefix of the 64 (round, wave) counts across wave 0
+        static_assert(kVisRounds * kWavesPerBlock == kWave, "one count per lane of wave 0");
+        const int c = s_cnt[threadIdx.x];
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(incl, off);
+            if ((int)threadIdx.x >= off) incl += y;
         }
-        s_base = run > 0 ? atomicAdd(count, run) : 0;
+        s_cnt[threadIdx.x] = incl - c;
+        const int total = __shfl(incl, kWave - 1);
+        if (threadIdx.x == 0) s_base = total > 0 ? atomicAdd(count, total) : 0;
     }
     __syncthreads();
 #pragma unroll

@@ -194,8 +194,10 @@ def test_step_zero_state_and_zero_gradients():
     compare(after, before, og, spec, t_ref, mask.astype(bool), False, "zero-state")
     op = after["opacity"]["param"][: n // 2, 0]
     vis = mask[: n // 2] == 1
-    np.testing.assert_array_equal(op[vis], (before["opacity"]["param"][: n // 2, 0][vis] - np.float32(0.05) *
-                                            np.float32(10.0)))
+    # theta - lr*C with lr*C = 0.5; the kernel may fuse the multiply-add, so
+    # allow one FP32 rounding of theta (|theta| < 8 here)
+    np.testing.assert_allclose(op[vis], before["opacity"]["param"][: n // 2, 0][vis].astype(np.float64) - 0.5,
+                               rtol=0, atol=4.8e-7)
 
 
 def test_schedules_give_identical_bits():
