@@ -5,26 +5,32 @@ attributes each (mean 3, log-scale 3, quaternion 4, opacity logit 1, SH 48),
 means uniform in [-10, 10]^3, every other attribute N(0, 1); 200 cameras on
 a radius-15 Fibonacci sphere looking at the origin (60 deg FOV, 1000 x 1000,
 z_near 0.2, z_far 17.5), one camera per step from a seeded shuffle; photometric
-gradients N(0, 1e-3); DAR with lambda_o = 1e-3, lambda_s = 1e-5, C = 10,
-N_I' = 1e5; RSR every 100 iterations with p = 0.05, alpha = (0.2, 0.04).
+gradients N(0, 1e-3) (four pre-drawn sets, rotated per step); DAR with
+lambda_o = 1e-3, lambda_s = 1e-5, C = 10, N_I' = 1e5; RSR every 100 iterations
+with p = 0.05, alpha = (0.2, 0.04).
+
+Layout: before timing, the scene is put in spatial (Morton) order with the
+library's gs_spatial_order + gs_gather_rows, so that a view's visible rows
+form contiguous index runs (--order index keeps the generated order).
 
 One step = visibility + compaction of the view, Re-State rescale (on RSR
 iterations) and the fused Sparse-Adam + DAR pass, all in the HIP library.
 Inputs are resident in HBM before timing starts.  The metric is attribute
 updates per second (visible primitives x 59 per step / wall time of the
 steps).  The JSON line also carries the roofline of the dominant kernel
-(the fused step) measured with HIP events on the launch stream, and the FP64
-oracle timed on the host over a bounded sample of the same workload.
+(the fused step) measured with HIP events on the launch stream, the FP64
+oracle timed on the host over a bounded sample of the same workload, and the
+other layouts / moment precisions measured the same way ("variants").
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+       [--order morton|index] [--moments f32|bf16] [--no-variants] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -41,9 +47,13 @@ STEP_LAUNCH = {"schedule": 1, "unit": 64}           # compacted schedule, 64 row
 
 N_PRIMS = 3_000_000
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_VISIBLE_F32 = 59 * 28 + 8 + 4             # theta r/w, g r, m r/w, v r/w; t r/w; index read
+# algorithmic bytes per visible primitive of the step kernel: theta r/w, g r,
+# m r/w, v r/w over 59 elements; t r/w; its visible-index read
+BYTES_PER_VISIBLE = {"f32": 59 * (4 + 4 + 4 + 4 + 4 + 4 + 4) + 8 + 4,      # 1664
+                     "bf16": 59 * (4 + 4 + 4 + 2 + 2 + 2 + 2) + 8 + 4}     # 1192
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
+N_GRAD_SETS = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")
 
 
@@ -55,15 +65,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(order: str, moments: str):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and layout."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash() or d.get("order") != order or d.get("moments") != moments:
         return None
     return d.get("bytes_per_launch")
 
@@ -118,11 +128,190 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
     return 0
 
 
+class SceneOnDevice:
+    """The scene's attributes and gradient sets in HBM, in a chosen order."""
+
+    def __init__(self, gs, torch, scene, order: str):
+        import synth
+        dev = torch.device("cuda:0")
+        self.params = [torch.from_numpy(scene.params[name]).to(dev) for name, *_ in synth.GROUPS_59]
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(0)
+        self.grads = [[torch.randn((N_PRIMS, dim), generator=gen, device=dev) * 1e-3 for _ in range(N_GRAD_SETS)]
+                      for _, dim, _, _ in synth.GROUPS_59]
+        self.order = order
+        if order == "morton":
+            perm = torch.empty(N_PRIMS, dtype=torch.int32, device=dev)
+            ws = torch.empty(gs.gs_spatial_order_workspace_size(N_PRIMS), dtype=torch.uint8, device=dev)
+            gs.gs_spatial_order(self.params[0], perm, ws)
+            self.params = gs.apply_spatial_order(self.params, perm)
+            self.grads = [gs.apply_spatial_order(sets, perm) for sets in self.grads]
+            del ws, perm
+        torch.cuda.synchronize()
+
+
+def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: int, warmup: int):
+    """Times `steps` whole steps (after `warmup`) on fresh optimizer state."""
+    import synth
+    dev = torch.device("cuda:0")
+    mdt = torch.bfloat16 if moments == "bf16" else torch.float32
+    groups = []
+    for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads):
+        groups.append(gs.Group(p.clone(), sets[0], torch.zeros((N_PRIMS, dim), dtype=mdt, device=dev),
+                               torch.zeros((N_PRIMS, dim), dtype=mdt, device=dev), lr, dar_kind=dar,
+                               dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0),
+                               dar_clip=CLIP))
+    total = warmup + steps
+    t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    counts = torch.zeros(total, dtype=torch.int32, device=dev)
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    means = groups[0].param
+    stream = torch.cuda.current_stream()
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    mom = gs.GS_MOMENT_BF16 if moments == "bf16" else gs.GS_MOMENT_F32
+
+    def one_step(k: int, slot: int = -1):
+        cnt = counts[k:k + 1]
+        gs.gs_visibility(means, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        for G, sets in zip(groups, sd.grads):
+            G.grad = sets[k % N_GRAD_SETS]
+        cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
+                            rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, moment_dtype=mom,
+                            stochastic_round=True, **STEP_LAUNCH)
+        if slot >= 0:
+            ev_s[slot].record(stream)
+        gs.adamw_gs_step(groups, N_PRIMS, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        if slot >= 0:
+            ev_e[slot].record(stream)
+
+    for k in range(warmup):
+        one_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps):
+        one_step(warmup + j, j)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    nv = counts.cpu().numpy()[warmup:].astype(np.int64)
+    durs = np.array([ev_s[j].elapsed_time(ev_e[j]) for j in range(steps)]) * 1e-3
+    plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
+    step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments]
+    achieved = float(step_bytes.sum() / durs[plain].sum()) / 1e9 if plain.any() else float("nan")
+    del groups, t, mask, idx
+    torch.cuda.empty_cache()
+    return {
+        "value": int(nv.sum()) * 59 / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "visible_mean": float(nv.mean()),
+        "achieved_GBps": achieved,
+        "step_kernel_us": float(durs[plain].mean() * 1e6) if plain.any() else float("nan"),
+    }
+
+
+def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8):
+    """Many-scene workload: 16 scenes with sizes log-uniform in [2e5, 4e6] and
+    visible ratios U[0.02, 0.60] (Bernoulli visibility, 8 pre-drawn masks per
+    scene used in turn), 59 attributes each.  Times three forms of the same
+    steps: the BF16-moment plan (one persistent launch per step from a HIP
+    graph, schedules picked by the tuner; one plan per mask set), and
+    per-scene adamw_gs_step calls with FP32 and with BF16 moments.  Every
+    form includes the compaction of the compacted scenes' masks."""
+    import synth
+    dev = torch.device("cuda:0")
+    sizes, ratios = synth.batch_scene_sizes(16, seed=0)
+    dims = [d for _, d, _, _ in synth.GROUPS_59]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    scenes = []
+    for n, p in zip(sizes.tolist(), ratios.tolist()):
+        sched, unit = gs.gs_tune(n, dims, float(p), gs.GS_MOMENT_BF16)
+        scenes.append(dict(
+            n=n, p=p, sched=sched,
+            params=[torch.randn((n, d), generator=gen, device=dev) for d in dims],
+            grads=[torch.randn((n, d), generator=gen, device=dev) * 1e-3 for d in dims],
+            masks=[(torch.rand(n, generator=gen, device=dev) < p).to(torch.uint8) for _ in range(n_masks)],
+            idx=[torch.zeros(n, dtype=torch.int32, device=dev) for _ in range(n_masks)],
+            cnt=[torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(n_masks)]))
+    stream = torch.cuda.current_stream()
+
+    def make_groups(sc, mdt):
+        return [gs.Group(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev),
+                         torch.zeros(p.shape, dtype=mdt, device=dev), lr, dar_kind=dar,
+                         dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+                for (name, d, lr, dar), p, g in zip(synth.GROUPS_59, sc["params"], sc["grads"])]
+
+    def timed(form):
+        bf16 = form != "per_scene_f32"
+        mdt = torch.bfloat16 if bf16 else torch.float32
+        mom = gs.GS_MOMENT_BF16 if bf16 else gs.GS_MOMENT_F32
+        state = [dict(groups=make_groups(sc, mdt), t=torch.zeros(sc["n"], dtype=torch.int32, device=dev))
+                 for sc in scenes]
+        plans = []
+        if form == "batched_bf16":
+            for r in range(n_masks):
+                plans.append(gs.Batch([gs.Scene(groups=st["groups"], n=sc["n"], step_count=st["t"],
+                                                visible=sc["masks"][r], vis_idx=sc["idx"][r],
+                                                vis_count=sc["cnt"][r], schedule=sc["sched"],
+                                                visible_hint=sc["p"]) for sc, st in zip(scenes, state)],
+                                      moment_dtype=mom))
+
+        def one(k):
+            r = k % n_masks
+            for sc in scenes:
+                if sc["sched"] == gs.GS_SCHED_COMPACTED:
+                    gs.gs_compact(sc["masks"][r], sc["idx"][r], sc["cnt"][r], stream=stream)
+            cfg = dict(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0), rsr_ratio=RSR_P,
+                       rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, moment_dtype=mom, stochastic_round=True)
+            if plans:
+                plans[r].step(gs.StepConfig(**cfg), stream=stream)
+            else:
+                for s, (sc, st) in enumerate(zip(scenes, state)):
+                    gs.adamw_gs_step(st["groups"], sc["n"], st["t"],
+                                     gs.StepConfig(**dict(cfg, seed=s, schedule=sc["sched"])),
+                                     visible=sc["masks"][r], vis_idx=sc["idx"][r], vis_count=sc["cnt"][r],
+                                     stream=stream)
+
+        for k in range(warmup):
+            one(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup, warmup + steps):
+            one(k)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for b in plans:
+            b.close()
+        del state, plans
+        torch.cuda.empty_cache()
+        return wall
+
+    vis_per_mask = [sum(int(sc["masks"][r].sum().item()) for sc in scenes) for r in range(n_masks)]
+    vis_total = sum(vis_per_mask[k % n_masks] for k in range(warmup, warmup + steps))
+    out = {"workload": "16 scenes, N log-uniform in [2e5, 4e6] (sum %d), visible 2-60 %%, 59 attributes, %d steps"
+                       % (int(sizes.sum()), steps),
+           "schedules": {"compacted": sum(sc["sched"] == gs.GS_SCHED_COMPACTED for sc in scenes),
+                         "masked": sum(sc["sched"] == gs.GS_SCHED_MASKED for sc in scenes)},
+           "visible_per_step": vis_total / steps}
+    for form in ("batched_bf16", "per_scene_bf16", "per_scene_f32"):
+        wall = timed(form)
+        out[form] = {"value": vis_total * 59 / wall, "ms_per_step": wall / steps * 1e3}
+    scenes.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--order", choices=["morton", "index"], default="morton")
+    ap.add_argument("--moments", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -140,103 +329,69 @@ def main(argv=None) -> int:
     import paper_2601_16736_amd as gs
     import synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     print(f"bench: generating the {N_PRIMS}-primitive scene", file=sys.stderr, flush=True)
     scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
     cams = synth.camera_rig()
-    total = args.warmup + args.steps
-    order = synth.camera_order(len(cams), total, seed=0)
+    order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
 
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(0)
-    n_grad_sets = 4
-    groups, grad_sets = [], []
-    for name, dim, lr, dar in synth.GROUPS_59:
-        p = torch.from_numpy(scene.params[name]).to(dev)
-        sets = [torch.randn((N_PRIMS, dim), generator=gen, device=dev) * 1e-3 for _ in range(n_grad_sets)]
-        grad_sets.append(sets)
-        groups.append(gs.Group(p, sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
-                               dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0),
-                               dar_clip=CLIP))
-    t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
-    mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
-    idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
-    counts = torch.zeros(total, dtype=torch.int32, device=dev)
-    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
-    means = groups[0].param
-    stream = torch.cuda.current_stream()
-    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    layouts = {args.order: SceneOnDevice(gs, torch, scene, args.order)}
+    print(f"bench: {args.order} order, {args.moments} moments: {args.steps} steps", file=sys.stderr, flush=True)
+    head = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup)
 
-    def one_step(k: int, timed_slot: int = -1):
-        cnt = counts[k:k + 1]
-        gs.gs_visibility(means, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
-        for G, sets in zip(groups, grad_sets):
-            G.grad = sets[k % n_grad_sets]
-        cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
-                            rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **STEP_LAUNCH)
-        if timed_slot >= 0:
-            ev_s[timed_slot].record(stream)
-        gs.adamw_gs_step(groups, N_PRIMS, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
-        if timed_slot >= 0:
-            ev_e[timed_slot].record(stream)
-
-    print(f"bench: warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        one_step(k)
-    torch.cuda.synchronize()
-    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for j in range(args.steps):
-        one_step(args.warmup + j, j)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    nv = counts.cpu().numpy()[args.warmup:].astype(np.int64)
-    updates = int(nv.sum()) * 59
-    value = updates / wall
-    durs = np.array([ev_s[j].elapsed_time(ev_e[j]) for j in range(args.steps)]) * 1e-3     # seconds
-    plain = np.array([(args.warmup + j) % RSR_EVERY != 0 for j in range(args.steps)])
-    step_bytes = nv[plain] * BYTES_PER_VISIBLE_F32
-    achieved_gbs = float(step_bytes.sum() / durs[plain].sum()) / 1e9
-    traffic = measured_traffic()
+    variants = []
+    if not args.no_variants:
+        for o, mo in (("index", "f32"), ("morton", "f32"), ("morton", "bf16"), ("index", "bf16")):
+            if (o, mo) == (args.order, args.moments):
+                continue
+            if o not in layouts:
+                layouts[o] = SceneOnDevice(gs, torch, scene, o)
+            print(f"bench: variant {o} order, {mo} moments", file=sys.stderr, flush=True)
+            r = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup)
+            r.update({"order": o, "moments": mo, "frac": r["achieved_GBps"] / HBM_PEAK_GBS})
+            variants.append(r)
+        del layouts
+        torch.cuda.empty_cache()
+        print("bench: variant batched 16 scenes", file=sys.stderr, flush=True)
+        variants.append({"batched": run_batched(gs, torch)})
 
     out = {
         "metric": "primitive-attr updates/s + % HBM roofline, fused AdamW-GS vs plain, 3M Gaussians",
-        "value": value,
+        "value": head["value"],
         "unit": "attr-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.moments == "f32" else "f32 (bf16 moment storage)",
         "data": "synthetic",
         "config": {
             "workload": "3M-primitive scene, 59 FP32 attributes per Gaussian, 200-camera rig (z_far 17.5), "
                         "visibility + compaction + RSR + fused Sparse-Adam/DAR step",
             "n_primitives": N_PRIMS,
-            "visible_mean": float(nv.mean()),
-            "visible_frac": float(nv.mean() / N_PRIMS),
+            "primitive_order": args.order,
+            "moments": args.moments,
+            "visible_mean": head["visible_mean"],
+            "visible_frac": head["visible_mean"] / N_PRIMS,
             "schedule": "compacted",
             "unit_rows": STEP_LAUNCH["unit"],
-            "moments": "f32",
         },
         "roofline": {
             "bound": "hbm",
             "kernel": "step_kernel (fused Sparse-Adam + DAR)",
-            "achieved": achieved_gbs,
+            "achieved": head["achieved_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "step_kernel_us": float(durs[plain].mean() * 1e6),
-            "bytes_per_visible": BYTES_PER_VISIBLE_F32,
+            "frac": head["achieved_GBps"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(args.order, args.moments),
+            "step_kernel_us": head["step_kernel_us"],
+            "bytes_per_visible": BYTES_PER_VISIBLE[args.moments],
         },
         "cpu_baseline": None,
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

@@ -226,21 +226,27 @@ typedef struct {
 typedef struct gs_batch gs_batch;
 
 /*
- * Builds a plan for n_scenes scenes: validates them, picks each scene's
- * schedule, uploads the scene table to device memory and prepares a HIP
- * graph holding the one persistent launch.  Allocates (device table, work
- * queue counters); the step calls below do not.  The arrays the scenes
- * point to must stay alive and in place while the plan is used.
+ * Builds a plan for 1..64 scenes whose moments are all stored as
+ * moment_dtype: validates them, picks each scene's schedule (and wave unit),
+ * uploads the scene table to device memory and sizes a persistent grid from
+ * the kernel's occupancy.  Allocates (device table, two work-queue counters)
+ * and synchronizes the device; the step calls below do not allocate.  The
+ * arrays the scenes point to must stay alive and in place while the plan is
+ * used; vis_count values are read on the device at each step.
  */
-gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, gs_batch** out);
+gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, int32_t moment_dtype, gs_batch** out);
 
 /*
  * One AdamW-GS step for every scene of the plan, as if adamw_gs_step were
  * called once per scene s with cfg->seed + s as the seed (so the scenes'
- * RSR samples and rounding draws are independent).  cfg->schedule and
- * cfg->unit are ignored (the plan fixed them).  Replays the plan's graph
- * (first call on a plan instantiates it); calls on one plan must not
- * overlap in time (they share the plan's work-queue counters).
+ * RSR samples and rounding draws are independent); the results are bit for
+ * bit those of the per-scene calls.  cfg->schedule, cfg->unit and
+ * cfg->visible_hint are ignored (the plan fixed them); cfg->moment_dtype must
+ * equal the plan's.  One persistent kernel serves every scene's step units
+ * and, when RSR runs, every scene's Re-State windows, pulling them from a
+ * work queue; it is replayed from a HIP graph (the first call instantiates
+ * it, later calls only replace its arguments).  Calls on one plan must not
+ * overlap in time: they share the plan's work-queue counters.
  */
 gs_status adamw_gs_step_batched(gs_batch* batch, const gs_step_config* cfg, hipStream_t stream);
 

@@ -24,6 +24,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2601_16736_amd.build` "
                       "(or __graft_entry__.build()) first")
 
+# torch ships its own HIP runtime (soname libamdhip64.so.7, loaded by another
+# file name).  Loading torch first makes this library's libamdhip64.so.7
+# dependency resolve to that already-loaded runtime, so tensors, streams and
+# these kernels share one runtime; loading this library first would bring in
+# a second runtime that finds no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 GS_OK, GS_EINVAL, GS_EHIP, GS_ENOMEM, GS_EUNSUPPORTED = 0, 1, 2, 3, 4
@@ -87,7 +94,7 @@ _lib.adamw_gs_step.restype = _i32
 _lib.adamw_gs_step.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, _vp, _vp,
                                ctypes.POINTER(gs_step_config), _vp]
 _lib.gs_batch_create.restype = _i32
-_lib.gs_batch_create.argtypes = [ctypes.POINTER(gs_scene), _i32, ctypes.POINTER(_vp)]
+_lib.gs_batch_create.argtypes = [ctypes.POINTER(gs_scene), _i32, _i32, ctypes.POINTER(_vp)]
 _lib.adamw_gs_step_batched.restype = _i32
 _lib.adamw_gs_step_batched.argtypes = [_vp, ctypes.POINTER(gs_step_config), _vp]
 _lib.gs_batch_scene_schedule.restype = _i32
@@ -283,8 +290,9 @@ class Scene:
 class Batch:
     """Plan for stepping many scenes in one persistent launch."""
 
-    def __init__(self, scenes: Sequence[Scene]):
+    def __init__(self, scenes: Sequence[Scene], moment_dtype: int = GS_MOMENT_F32):
         self._scenes = list(scenes)              # keeps tensors alive
+        self.moment_dtype = int(moment_dtype)
         self._garr = [_groups_c(s.groups) for s in self._scenes]
         sarr = (gs_scene * len(self._scenes))()
         for k, s in enumerate(self._scenes):
@@ -298,7 +306,7 @@ class Batch:
             sarr[k].visible_hint = float(s.visible_hint)
             sarr[k].reserved = 0
         h = _vp()
-        _check(_lib.gs_batch_create(sarr, len(self._scenes), ctypes.byref(h)))
+        _check(_lib.gs_batch_create(sarr, len(self._scenes), self.moment_dtype, ctypes.byref(h)))
         self._h = h
 
     def schedule(self, s: int) -> int:
@@ -319,8 +327,8 @@ class Batch:
             pass
 
 
-def gs_batch_create(scenes: Sequence[Scene]) -> Batch:
-    return Batch(scenes)
+def gs_batch_create(scenes: Sequence[Scene], moment_dtype: int = GS_MOMENT_F32) -> Batch:
+    return Batch(scenes, moment_dtype)
 
 
 def adamw_gs_step_batched(batch: Batch, cfg: StepConfig, stream=None) -> None:

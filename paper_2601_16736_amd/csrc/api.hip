@@ -100,14 +100,11 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
         K.lr = (float)G.lr;
         K.dar_kind = G.dar_kind;
         K.reg_mode = G.reg_mode;
-        if (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
-            K.dar_scale = (float)(G.dar_lambda / cfg->reg_norm);
-        else
-            K.dar_scale = (float)G.dar_lambda;
         K.dar_clip = std::isinf(G.dar_clip) ? INFINITY : (float)G.dar_clip;
-        K.sr_s1 = splitmix_output(cfg->seed, kTagSrStep + (uint64_t)g + 1);
-        K.rsr_sr_s1 = splitmix_output(cfg->seed, kTagSrRsr + (uint64_t)g + 1);
+        K.pad = 0;
+        K.dar_lambda = G.dar_lambda;
     }
+    (void)cfg;
     for (int g = n_groups; g < GS_MAX_GROUPS; ++g) memset(&out->g[g], 0, sizeof(KGroup));
     out->n_groups = n_groups;
     out->bf16 = bf16 ? 1 : 0;
@@ -153,7 +150,8 @@ gs_status build_hyper(const gs_step_config* cfg, bool need_reg_norm, KHyper* h)
         else if (cfg->rsr_ratio > 0.0) thr = (uint64_t)std::floor(cfg->rsr_ratio * 4294967296.0);
     }
     h->rsr_thr = thr;
-    h->rsr_s1 = splitmix_output(cfg->seed, kTagRsr + 1);
+    h->seed = cfg->seed;
+    h->reg_norm = cfg->reg_norm;
     h->iteration = cfg->iteration;
     return GS_OK;
 }

@@ -1,25 +1,325 @@
-// Many scenes in one persistent launch (placeholder until the plan kernel lands).
-#include "internal.h"
+// Many scenes in one persistent launch.
+//
+// A plan holds the scenes' kernel views in device memory.  Each step is one
+// launch of a persistent grid (sized from the kernel's occupancy) whose waves
+// pull work units from a global atomic counter: first every scene's step
+// units (index-list slices or mask windows, per the scene's schedule), then,
+// on Re-State iterations, every scene's windows of invisible sampled rows.
+// The last wave to finish resets the counters, so consecutive launches need
+// no clearing.  The launch is a HIP graph with one kernel node whose
+// arguments (the step's scalars) are replaced before each replay.
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
 
 namespace gs {
+
 gs_status set_error(gs_status s, const char* msg);
-}
+void clear_error();
+gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int32_t moment_dtype,
+                       const gs_step_config* cfg, KScene* out, const char* prefix);
+gs_status build_hyper(const gs_step_config* cfg, bool need_reg_norm, KHyper* h);
+gs_status resolve_schedule(int requested, int unit, float hint, int64_t n, int n_groups, const int32_t* dims,
+                           int dtype, const uint8_t* mask, const int32_t* idx, const int32_t* count,
+                           int* sched_out, int* unit_out, const char* prefix);
 
-extern "C" {
+namespace {
 
-gs_status gs_batch_create(const gs_scene*, int32_t, gs_batch** out)
+constexpr int kMaxScenes = kWave;     // one lane per scene when counting units
+constexpr int kBatchCap = 512;
+constexpr int kRsrWindow = 512;
+
+struct KBatch {
+    const KScene* scenes;
+    int32_t n_scenes;
+    int32_t rsr;          // Re-State units for invisible sampled rows this step
+    int32_t* queue;       // [0] next unit, [1] waves finished
+    int32_t total_waves;
+    int32_t pad;
+};
+
+__device__ __forceinline__ int scene_step_units(const KScene& S)
 {
-    if (out) *out = nullptr;
-    return gs::set_error(GS_EUNSUPPORTED, "gs_batch_create: not built yet");
+    if (S.sched == kSchedCompacted) {
+        const int cnt = (int)min((int64_t)*S.count, S.n);
+        return cnt > 0 ? (cnt + S.unit - 1) / S.unit : 0;
+    }
+    return (int)((S.n + S.unit - 1) / S.unit);
 }
 
-gs_status adamw_gs_step_batched(gs_batch*, const gs_step_config*, hipStream_t)
+__device__ __forceinline__ int scene_rsr_units(const KScene& S, int rsr)
 {
-    return gs::set_error(GS_EUNSUPPORTED, "adamw_gs_step_batched: not built yet");
+    return (rsr && S.sched != kSchedDense && S.mask != nullptr) ? (int)((S.n + kRsrWindow - 1) / kRsrWindow) : 0;
 }
 
-int32_t gs_batch_scene_schedule(const gs_batch*, int32_t) { return -1; }
+template <bool BF16>
+__device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, float* s_rb1,
+                                          float* s_rsb2, int lane)
+{
+    int nrows = 0;
+    if (S.sched == kSchedCompacted) {
+        const int cnt = (int)min((int64_t)*S.count, S.n);
+        const int64_t base = local * S.unit;
+        switch (S.unit) {
+        case 64: nrows = build_rows_slice<64>(S.idx, cnt, S.n, base, s_row, lane); break;
+        case 128: nrows = build_rows_slice<128>(S.idx, cnt, S.n, base, s_row, lane); break;
+        case 256: nrows = build_rows_slice<256>(S.idx, cnt, S.n, base, s_row, lane); break;
+        default: nrows = build_rows_slice<512>(S.idx, cnt, S.n, base, s_row, lane); break;
+        }
+    } else {
+        const int64_t w0 = local * S.unit;
+        const uint8_t* mask = S.sched == kSchedMasked ? S.mask : nullptr;
+        switch (S.unit) {
+        case 128: nrows = build_rows_window<128>(mask, S.n, w0, s_row, lane); break;
+        case 256: nrows = build_rows_window<256>(mask, S.n, w0, s_row, lane); break;
+        default: nrows = build_rows_window<512>(mask, S.n, w0, s_row, lane); break;
+        }
+    }
+    if (nrows > 0) {
+        const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
+        wave_sync();
+        stage_step_rows(nrows, s_row, s_rb1, s_rsb2, S.t, H, d_stream(seed, kTagRsr, H.iteration), lane);
+        wave_sync();
+        step_all_groups<BF16>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
+    }
+    wave_sync();   // the next unit reuses this wave's LDS rows
+}
 
-gs_status gs_batch_destroy(gs_batch*) { return GS_OK; }
+template <bool BF16>
+__device__ __forceinline__ void rsr_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, int lane)
+{
+    const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
+    const uint64_t s2 = d_stream(seed, kTagRsr, H.iteration);
+    const int nrows = build_rows_sampled<kRsrWindow>(S.mask, S.n, local * kRsrWindow, s2, H.rsr_thr, s_row, lane);
+    if (nrows > 0) {
+        wave_sync();
+        rsr_all_groups<BF16>(S, H, seed, nrows, s_row, lane);
+    }
+    wave_sync();
+}
 
+template <bool BF16>
+__global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
+{
+    __shared__ int s_row[kWavesPerBlock][kBatchCap];
+    __shared__ float s_rb1[kWavesPerBlock][kBatchCap];
+    __shared__ float s_rsb2[kWavesPerBlock][kBatchCap];
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+
+    // units of scene `lane`, and their running total over the scenes
+    int su = 0, ru = 0;
+    if (lane < B.n_scenes) {
+        const KScene& S = B.scenes[lane];
+        su = scene_step_units(S);
+        ru = scene_rsr_units(S, B.rsr);
+    }
+    const int mine = su + ru;
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+
+    for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(&B.queue[0], 1);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
+        if (u >= total) break;
+        const uint64_t owner = __ballot(lane < B.n_scenes && incl > u);
+        const int s = __ffsll((unsigned long long)owner) - 1;
+        const int start = __builtin_amdgcn_readfirstlane(__shfl(incl - mine, s));
+        const int steps_s = __builtin_amdgcn_readfirstlane(__shfl(su, s));
+        const KScene& S = B.scenes[s];
+        const int local = u - start;
+        if (local < steps_s) step_unit<BF16>(S, H, local, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+        else rsr_unit<BF16>(S, H, local - steps_s, s_row[wave], lane);
+    }
+
+    // every wave checks out; the last one resets the counters for the next launch
+    if (lane == 0) {
+        const int done = atomicAdd(&B.queue[1], 1);
+        if (done == B.total_waves - 1) {
+            atomicExch(&B.queue[0], 0);
+            atomicExch(&B.queue[1], 0);
+        }
+    }
+}
+
+}  // namespace
+
+}  // namespace gs
+
+using namespace gs;
+
+struct gs_batch {
+    int32_t n_scenes = 0;
+    int32_t moment_dtype = 0;
+    bool any_adaptive = false;
+    std::vector<KScene> h_scenes;
+    std::vector<int32_t> sched;
+    KScene* d_scenes = nullptr;
+    int32_t* d_queue = nullptr;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+    hipEvent_t done = nullptr;
+    KBatch kb{};
+    KHyper kh{};
+};
+
+namespace {
+
+void* kernel_for(int moment_dtype)
+{
+    return moment_dtype == GS_MOMENT_BF16 ? reinterpret_cast<void*>(&batched_kernel<true>)
+                                          : reinterpret_cast<void*>(&batched_kernel<false>);
+}
+
+void free_batch(gs_batch* b)
+{
+    if (b == nullptr) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->d_scenes) (void)hipFree(b->d_scenes);
+    if (b->d_queue) (void)hipFree(b->d_queue);
+    delete b;
+}
+
+gs_status fail_batch(gs_batch* b, gs_status s, const char* msg)
+{
+    free_batch(b);
+    return set_error(s, msg);
+}
+
+}  // namespace
+
+extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, int32_t moment_dtype, gs_batch** out)
+{
+    clear_error();
+    if (out == nullptr) return set_error(GS_EINVAL, "gs_batch_create: out is NULL");
+    *out = nullptr;
+    if (scenes == nullptr || n_scenes < 1 || n_scenes > kMaxScenes)
+        return set_error(GS_EINVAL, "gs_batch_create: need 1..64 scenes");
+    if (moment_dtype != GS_MOMENT_F32 && moment_dtype != GS_MOMENT_BF16)
+        return set_error(GS_EINVAL, "gs_batch_create: unknown moment_dtype");
+    gs_batch* b = new gs_batch();
+    b->n_scenes = n_scenes;
+    b->moment_dtype = moment_dtype;
+    b->h_scenes.resize((size_t)n_scenes);
+    b->sched.resize((size_t)n_scenes);
+    gs_step_config dummy;
+    memset(&dummy, 0, sizeof dummy);
+    for (int s = 0; s < n_scenes; ++s) {
+        const gs_scene& sc = scenes[s];
+        char prefix[64];
+        snprintf(prefix, sizeof prefix, "gs_batch_create: scene %d: ", s);
+        if (sc.n < 0 || sc.n >= ((int64_t)1 << 31)) return fail_batch(b, GS_EINVAL, "gs_batch_create: scene n out of range");
+        if (sc.reserved != 0) return fail_batch(b, GS_EINVAL, "gs_batch_create: reserved must be 0");
+        if (sc.n > 0 && sc.step_count == nullptr) return fail_batch(b, GS_EINVAL, "gs_batch_create: step_count is NULL");
+        if ((uintptr_t)sc.step_count % 4 || (uintptr_t)sc.vis_count % 4 || (uintptr_t)sc.vis_idx % 4)
+            return fail_batch(b, GS_EINVAL, "gs_batch_create: misaligned step_count / vis_idx / vis_count");
+        KScene& K = b->h_scenes[(size_t)s];
+        memset(&K, 0, sizeof K);
+        gs_status st = build_groups(sc.groups, sc.n_groups, sc.n, moment_dtype, &dummy, &K, prefix);
+        if (st != GS_OK) {
+            free_batch(b);
+            return st;
+        }
+        int32_t dims[GS_MAX_GROUPS];
+        for (int g = 0; g < sc.n_groups; ++g) {
+            dims[g] = sc.groups[g].dim;
+            if (sc.groups[g].dar_kind != GS_DAR_NONE && sc.groups[g].reg_mode == GS_REG_ADAPTIVE) b->any_adaptive = true;
+        }
+        int sched = 0, unit = 0;
+        st = resolve_schedule(sc.schedule, 0, sc.visible_hint, sc.n, sc.n_groups, dims, moment_dtype, sc.visible,
+                              sc.vis_idx, sc.vis_count, &sched, &unit, prefix);
+        if (st != GS_OK) {
+            free_batch(b);
+            return st;
+        }
+        K.sched = sched;
+        K.unit = unit;
+        K.seed_offset = s;
+        K.mask = sc.visible;
+        K.idx = sc.vis_idx;
+        K.count = sc.vis_count;
+        K.t = sc.step_count;
+        b->sched[(size_t)s] = sched;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(moment_dtype)),
+                                                     kBlock, 0) != hipSuccess)
+        return fail_batch(b, GS_EHIP, "gs_batch_create: device query failed");
+    b->grid = std::max(1, cus * std::max(1, per_cu));
+    if (hipMalloc(&b->d_scenes, sizeof(KScene) * (size_t)n_scenes) != hipSuccess ||
+        hipMalloc(&b->d_queue, 2 * sizeof(int32_t)) != hipSuccess)
+        return fail_batch(b, GS_ENOMEM, "gs_batch_create: hipMalloc failed");
+    if (hipMemcpy(b->d_scenes, b->h_scenes.data(), sizeof(KScene) * (size_t)n_scenes, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(b->d_queue, 0, 2 * sizeof(int32_t)) != hipSuccess || hipEventCreate(&b->done) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return fail_batch(b, GS_EHIP, "gs_batch_create: upload failed");
+    b->kb.scenes = b->d_scenes;
+    b->kb.n_scenes = n_scenes;
+    b->kb.queue = b->d_queue;
+    b->kb.total_waves = b->grid * kWavesPerBlock;
+    *out = b;
+    return GS_OK;
+}
+
+extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cfg, hipStream_t stream)
+{
+    clear_error();
+    if (b == nullptr) return set_error(GS_EINVAL, "adamw_gs_step_batched: batch is NULL");
+    if (cfg == nullptr) return set_error(GS_EINVAL, "adamw_gs_step_batched: cfg is NULL");
+    if (cfg->moment_dtype != b->moment_dtype)
+        return set_error(GS_EINVAL, "adamw_gs_step_batched: cfg->moment_dtype differs from the plan's");
+    KHyper h;
+    gs_status st = build_hyper(cfg, b->any_adaptive, &h);
+    if (st != GS_OK) return st;
+    b->kh = h;
+    b->kb.rsr = (cfg->rsr_enable && h.rsr_thr > 0) ? 1 : 0;
+    void* args[] = {&b->kb, &b->kh};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = kernel_for(b->moment_dtype);
+    p.gridDim = dim3((unsigned)b->grid);
+    p.blockDim = dim3(kBlock);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    hipError_t e = hipSuccess;
+    if (b->exec == nullptr) {
+        e = hipGraphCreate(&b->graph, 0);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&b->node, b->graph, nullptr, 0, &p);
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    } else {
+        e = hipGraphExecKernelNodeSetParams(b->exec, b->node, &p);
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, stream);
+    if (e == hipSuccess) e = hipEventRecord(b->done, stream);
+    if (e != hipSuccess) return set_error(GS_EHIP, hipGetErrorString(e));
+    return GS_OK;
+}
+
+extern "C" int32_t gs_batch_scene_schedule(const gs_batch* b, int32_t s)
+{
+    if (b == nullptr || s < 0 || s >= b->n_scenes) return -1;
+    return b->sched[(size_t)s];
+}
+
+extern "C" gs_status gs_batch_destroy(gs_batch* b)
+{
+    if (b == nullptr) return GS_OK;
+    if (b->done) (void)hipEventSynchronize(b->done);
+    free_batch(b);
+    return GS_OK;
 }

@@ -25,6 +25,13 @@ __device__ __forceinline__ uint64_t d_mix64(uint64_t z)
 
 __device__ __forceinline__ uint64_t d_splitmix(uint64_t s, uint64_t k) { return d_mix64(s + k * kGamma); }
 
+// State of the stream keyed by (seed, tag, iteration): output (tag+1) of the
+// stream seeded with `seed`, then output (iteration+1) of that one.
+__device__ __forceinline__ uint64_t d_stream(uint64_t seed, uint64_t tag, int64_t iteration)
+{
+    return d_splitmix(d_splitmix(seed, tag + 1), (uint64_t)iteration + 1);
+}
+
 // ---------------------------------------------------------------- bf16 storage
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
@@ -201,7 +208,7 @@ __device__ __forceinline__ float reg_term(int kind, int mode, float scale, float
 template <bool BF16, int V, int U>
 __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int nrows,
                                            const int* s_row, const float* s_rb1, const float* s_rsb2,
-                                           int lane, uint64_t sr_s2)
+                                           int lane, float dar_scale, uint64_t sr_s2)
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
@@ -254,7 +261,7 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
                 const float d = __fsqrt_rn(vv) * rsb2[u] + H.eps;       // sqrt(v / b2) + eps
                 float uu = (mm * rb1[u]) / d;                            // (m / b1) / d
 #endif
-                if (dar) uu += reg_term(G.dar_kind, G.reg_mode, G.dar_scale, G.dar_clip, th[u][q], d);
+                if (dar) uu += reg_term(G.dar_kind, G.reg_mode, dar_scale, G.dar_clip, th[u][q], d);
                 th[u][q] = th[u][q] - G.lr * uu;
                 m[u][q] = mm;
                 v[u][q] = vv;
@@ -371,9 +378,8 @@ __device__ __forceinline__ int build_rows_slice(const int32_t* idx, int cnt, int
 // 1/(1 - beta1^t) and 1/sqrt(1 - beta2^t), with 1 - beta^t = -expm1(t log beta).
 // A row in the Re-State sample gets its sign bit set (indices are < 2^31).
 __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_rb1, float* s_rsb2,
-                                                int32_t* t, const KHyper& H, int lane)
+                                                int32_t* t, const KHyper& H, uint64_t rsr_s2, int lane)
 {
-    const uint64_t rsr_s2 = d_splitmix(H.rsr_s1, (uint64_t)H.iteration + 1);
     for (int j = lane; j < nrows; j += kWave) {
         const int i = s_row[j];
         if (H.rsr_thr != 0 && rsr_sampled(rsr_s2, H.rsr_thr, i)) s_row[j] = (int)((uint32_t)i | 0x80000000u);
@@ -393,26 +399,31 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
 #endif
 
 template <bool BF16>
-__device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, int nrows, const int* s_row,
-                                                const float* s_rb1, const float* s_rsb2, int lane)
+__device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
+                                                const int* s_row, const float* s_rb1, const float* s_rsb2,
+                                                int lane)
 {
     constexpr int U = GS_STEP_UNROLL;
     for (int gi = 0; gi < S.n_groups; ++gi) {
         const KGroup& G = S.g[gi];
-        const uint64_t s2 = BF16 ? d_splitmix(G.sr_s1, (uint64_t)H.iteration + 1) : 0;
-        if (G.vec == 4) step_group<BF16, 4, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
-        else if (G.vec == 2) step_group<BF16, 2, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
-        else step_group<BF16, 1, U * 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2);
+        // lambda / N_I' rounded once from double, exactly as a host would form it
+        const float dar_scale = (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
+                                    ? (float)(G.dar_lambda / H.reg_norm)
+                                    : (float)G.dar_lambda;
+        const uint64_t s2 = BF16 ? d_stream(seed, kTagSrStep + (uint64_t)gi, H.iteration) : 0;
+        if (G.vec == 4) step_group<BF16, 4, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2);
+        else if (G.vec == 2) step_group<BF16, 2, U>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2);
+        else step_group<BF16, 1, U * 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2);
     }
 }
 
 template <bool BF16>
-__device__ __forceinline__ void rsr_all_groups(const KScene& S, const KHyper& H, int nrows, const int* s_row,
-                                               int lane)
+__device__ __forceinline__ void rsr_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
+                                               const int* s_row, int lane)
 {
     for (int gi = 0; gi < S.n_groups; ++gi) {
         const KGroup& G = S.g[gi];
-        const uint64_t s2 = BF16 ? d_splitmix(G.rsr_sr_s1, (uint64_t)H.iteration + 1) : 0;
+        const uint64_t s2 = BF16 ? d_stream(seed, kTagSrRsr + (uint64_t)gi, H.iteration) : 0;
         if (G.vec == 4) rsr_group<BF16, 4>(G, H, nrows, s_row, lane, s2);
         else if (G.vec == 2) rsr_group<BF16, 2>(G, H, nrows, s_row, lane, s2);
         else rsr_group<BF16, 1>(G, H, nrows, s_row, lane, s2);

@@ -29,10 +29,9 @@ struct KGroup {
     float lr;
     int32_t dar_kind;
     int32_t reg_mode;
-    float dar_scale;     // lambda / N_I' (adaptive) or lambda (constant modes)
     float dar_clip;
-    uint64_t sr_s1;      // SplitMix state after the group's step-rounding tag
-    uint64_t rsr_sr_s1;  // same for the RSR-rounding tag
+    int32_t pad;
+    double dar_lambda;   // lambda; the kernels form lambda / N_I' in double, as the host would
 };
 
 // Per-call scalars.
@@ -44,7 +43,8 @@ struct KHyper {
     float c1_rsr, c2_rsr;             // beta1*alpha1, beta2*alpha2: moment decay of a sampled visible row
     int32_t sr;                       // stochastic rounding of BF16 moments
     uint64_t rsr_thr;                 // sampled iff draw >> 32 < rsr_thr
-    uint64_t rsr_s1;                  // sampling stream state after the RSR tag (iteration applied on device)
+    uint64_t seed;                    // draws of scene s use seed + s (see KScene::seed_offset)
+    double reg_norm;                  // N_I'
     int64_t iteration;
 };
 
@@ -55,6 +55,7 @@ struct KScene {
     int32_t sched;
     int32_t unit;                      // rows (compacted) or primitives (masked/dense) per wave unit
     int32_t bf16;
+    int64_t seed_offset;               // added to the call's seed: 0, or the scene's place in a batch
     int64_t n;
     const uint8_t* mask;
     const int32_t* idx;

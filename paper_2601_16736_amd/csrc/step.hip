@@ -30,10 +30,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
         nrows = build_rows_window<UNIT>(SCHED == kSchedMasked ? S.mask : nullptr, S.n, w0, s_row[wave], lane);
     }
     if (nrows == 0) return;
+    const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
     wave_sync();
-    stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H, lane);
+    stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H, d_stream(seed, kTagRsr, H.iteration),
+                    lane);
     wave_sync();
-    step_all_groups<BF16>(S, H, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+    step_all_groups<BF16>(S, H, seed, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
 }
 
 // Re-State pass over the primitives the step does not visit (mask == 0):
@@ -50,11 +52,12 @@ __global__ __launch_bounds__(kBlock) void rsr_kernel(KScene S, KHyper H)
     const int lane = threadIdx.x % kWave;
     const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRsrUnit;
     if (w0 >= S.n) return;
-    const uint64_t s2 = d_splitmix(H.rsr_s1, (uint64_t)H.iteration + 1);
+    const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
+    const uint64_t s2 = d_stream(seed, kTagRsr, H.iteration);
     const int nrows = build_rows_sampled<kRsrUnit>(S.mask, S.n, w0, s2, H.rsr_thr, s_row[wave], lane);
     if (nrows == 0) return;
     wave_sync();
-    rsr_all_groups<BF16>(S, H, nrows, s_row[wave], lane);
+    rsr_all_groups<BF16>(S, H, seed, nrows, s_row[wave], lane);
 }
 
 namespace {

@@ -76,23 +76,36 @@ __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int6
     }
 }
 
+template <bool RADIUS>
 __global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restrict__ means,
                                                             const float* __restrict__ radius, int64_t n,
                                                             KCamera cam, uint8_t* __restrict__ mask,
                                                             int32_t* __restrict__ idx, int32_t* count)
 {
     const int64_t first = (int64_t)blockIdx.x * kVisPerBlock;
+    // every round's loads first (indices past the end read the last element
+    // and are discarded), so the 16 rounds' loads are in flight together
+    float x[kVisRounds], y[kVisRounds], z[kVisRounds], rho[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        const int64_t i = min(first + s * kBlock + threadIdx.x, n - 1);
+        x[s] = means[3 * i];
+        y[s] = means[3 * i + 1];
+        z[s] = means[3 * i + 2];
+        rho[s] = RADIUS ? radius[i] : 0.0f;
+    }
     bool vis[kVisRounds];
 #pragma unroll
     for (int s = 0; s < kVisRounds; ++s) {
         const int64_t i = first + s * kBlock + threadIdx.x;
-        bool v = false;
-        if (i < n) {
-            const float* mu = means + 3 * i;
-            v = visible_pred(mu[0], mu[1], mu[2], radius != nullptr ? radius + i : nullptr, cam);
-            if (mask != nullptr) mask[i] = (uint8_t)v;
+        vis[s] = i < n && visible_pred(x[s], y[s], z[s], RADIUS ? &rho[s] : nullptr, cam);
+    }
+    if (mask != nullptr) {
+#pragma unroll
+        for (int s = 0; s < kVisRounds; ++s) {
+            const int64_t i = first + s * kBlock + threadIdx.x;
+            if (i < n) mask[i] = (uint8_t)vis[s];
         }
-        vis[s] = v;
     }
     if (idx != nullptr) block_append(vis, first, idx, count);
 }
@@ -101,12 +114,12 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint8_t* __restri
                                                          int32_t* __restrict__ idx, int32_t* count)
 {
     const int64_t first = (int64_t)blockIdx.x * kVisPerBlock;
+    uint8_t m[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) m[s] = mask[min(first + s * kBlock + threadIdx.x, n - 1)];
     bool vis[kVisRounds];
 #pragma unroll
-    for (int s = 0; s < kVisRounds; ++s) {
-        const int64_t i = first + s * kBlock + threadIdx.x;
-        vis[s] = i < n && mask[i] != 0;
-    }
+    for (int s = 0; s < kVisRounds; ++s) vis[s] = first + s * kBlock + threadIdx.x < n && m[s] != 0;
     block_append(vis, first, idx, count);
 }
 
@@ -127,8 +140,12 @@ hipError_t launch_visibility(const float* means, const float* radius, int64_t n,
     }
     if (n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
-    hipLaunchKernelGGL(visibility_kernel, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam, mask,
-                       idx, count);
+    if (radius != nullptr)
+        hipLaunchKernelGGL(visibility_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam,
+                           mask, idx, count);
+    else
+        hipLaunchKernelGGL(visibility_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam,
+                           mask, idx, count);
     return hipGetLastError();
 }
 

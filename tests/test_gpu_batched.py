@@ -1,0 +1,130 @@
+"""Batched plan: one persistent launch over many scenes must give, bit for bit,
+what per-scene adamw_gs_step calls with seed + s give, on every graph
+replay (eager work and synchronisations in between), for mixed schedules,
+sizes, visibility ratios, RSR iterations and both moment precisions; and one
+scene is checked against the oracle directly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+gs = pytest.importorskip("paper_2601_16736_amd")
+from _gpu_util import DEV, compare, make_state, oracle_config, oracle_groups, rsr_sampled_mask  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def _clone_state(st):
+    groups = [gs.Group(g.param.clone(), g.grad.clone(), g.exp_avg.clone(), g.exp_avg_sq.clone(), g.lr,
+                       dar_kind=g.dar_kind, dar_lambda=g.dar_lambda, dar_clip=g.dar_clip, reg_mode=g.reg_mode)
+              for g in st.groups]
+    return groups, st.t.clone()
+
+
+SCENES = [  # (n, visible ratio, schedule, layout)
+    (30_001, 0.02, gs.GS_SCHED_COMPACTED, synth.GROUPS_59),
+    (257, 0.6, gs.GS_SCHED_MASKED, synth.GROUPS_59),
+    (75_000, 0.3, gs.GS_SCHED_COMPACTED, synth.GROUPS_60_SPLIT),
+    (4096, 1.0, gs.GS_SCHED_DENSE, synth.GROUPS_59),
+    (1, 1.0, gs.GS_SCHED_MASKED, synth.GROUPS_59),
+    (12_345, 0.45, gs.GS_SCHED_AUTO, synth.GROUPS_60_SPLIT),
+]
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_batched_equals_per_scene_calls(bf16):
+    rng = np.random.default_rng(3)
+    plans, refs = [], []
+    for s, (n, p, sched, spec) in enumerate(SCENES):
+        st = make_state(gs, n, spec, 100 + s, bf16=bf16)
+        for g in st.groups:
+            g.grad.copy_(torch.from_numpy((1e-3 * rng.standard_normal(tuple(g.grad.shape))).astype(np.float32)))
+        mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+        plans.append(dict(st=st, mask=mask, idx=idx, cnt=cnt, n=n, p=p, sched=sched, spec=spec))
+        rg, rt = _clone_state(st)
+        refs.append(dict(groups=rg, t=rt))
+    scenes = [gs.Scene(groups=d["st"].groups, n=d["n"], step_count=d["st"].t, visible=d["mask"],
+                       vis_idx=d["idx"], vis_count=d["cnt"], schedule=d["sched"], visible_hint=d["p"])
+              for d in plans]
+    batch = gs.Batch(scenes, moment_dtype=int(bf16))
+    for s, d in enumerate(plans):
+        assert batch.schedule(s) in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED, gs.GS_SCHED_DENSE)
+    for it in range(5):                       # five replays of the plan's graph
+        for s, d in enumerate(plans):         # eager work between replays: new masks + compaction
+            m = synth.bernoulli_mask(d["n"], d["p"], s, it)
+            d["mask"].copy_(torch.from_numpy(m))
+            gs.gs_compact(d["mask"], d["idx"], d["cnt"])
+        cfg = gs.StepConfig(iteration=it, seed=77, rsr_enable=(it % 2 == 1), rsr_ratio=0.25,
+                            moment_dtype=int(bf16), stochastic_round=True)
+        batch.step(cfg)
+        torch.cuda.synchronize()
+        for s, (d, r) in enumerate(zip(plans, refs)):
+            sched = batch.schedule(s)
+            c1 = gs.StepConfig(iteration=it, seed=77 + s, rsr_enable=(it % 2 == 1), rsr_ratio=0.25,
+                               moment_dtype=int(bf16), stochastic_round=True, schedule=sched)
+            gs.adamw_gs_step(r["groups"], d["n"], r["t"], c1, visible=d["mask"], vis_idx=d["idx"],
+                             vis_count=d["cnt"])
+        torch.cuda.synchronize()
+        for s, (d, r) in enumerate(zip(plans, refs)):
+            assert torch.equal(d["st"].t, r["t"]), f"replay {it} scene {s}: step counts"
+            for a, b in zip(d["st"].groups, r["groups"]):
+                assert torch.equal(a.param, b.param), f"replay {it} scene {s}: theta"
+                assert torch.equal(a.exp_avg.view(torch.int16) if bf16 else a.exp_avg,
+                                   b.exp_avg.view(torch.int16) if bf16 else b.exp_avg), f"replay {it} scene {s}: m"
+                assert torch.equal(a.exp_avg_sq.view(torch.int16) if bf16 else a.exp_avg_sq,
+                                   b.exp_avg_sq.view(torch.int16) if bf16 else b.exp_avg_sq)
+    batch.close()
+
+
+def test_batched_scene_against_oracle():
+    """Scene 1 of a 3-scene plan (seed offset 1) against the oracle."""
+    spec = synth.GROUPS_59
+    sts, masks = [], []
+    for s, n in enumerate((5000, 20_000, 999)):
+        st = make_state(gs, n, spec, 200 + s)
+        m = synth.bernoulli_mask(n, 0.3, 9, s)
+        gr = synth.grads(n, spec, m, 9, s)
+        for (name, *_), g in zip(spec, st.groups):
+            g.grad.copy_(torch.from_numpy(gr[name]))
+        sts.append(st)
+        masks.append(m)
+    d_masks = [torch.from_numpy(m).to(DEV) for m in masks]
+    scenes = [gs.Scene(groups=st.groups, n=st.t.shape[0], step_count=st.t, visible=dm,
+                       schedule=gs.GS_SCHED_MASKED) for st, dm in zip(sts, d_masks)]
+    batch = gs.Batch(scenes)
+    before = sts[1].host()
+    cfg = gs.StepConfig(iteration=100, seed=5, rsr_enable=True, rsr_ratio=0.05)
+    batch.step(cfg)
+    torch.cuda.synchronize()
+    og = oracle_groups(before, spec, sts[1].groups)
+    t_ref = before["_t"].copy()
+    ocfg = oracle_config(cfg)
+    ocfg.seed = 6                               # scene 1 draws with seed + 1
+    oracle.adamw_gs_step(og, 20_000, masks[1], t_ref, ocfg)
+    touched = masks[1].astype(bool) | rsr_sampled_mask(20_000, 6, 100, 0.05)
+    compare(sts[1].host(), before, og, spec, t_ref, touched, False, "batched scene 1")
+    batch.close()
+
+
+def test_batch_rejects_bad_plans():
+    st = make_state(gs, 10, synth.GROUPS_59, 1)
+    sc = gs.Scene(groups=st.groups, n=10, step_count=st.t, schedule=gs.GS_SCHED_COMPACTED)   # no index list
+    with pytest.raises(gs.GsError):
+        gs.Batch([sc])
+    with pytest.raises(gs.GsError):
+        gs.Batch([gs.Scene(groups=st.groups, n=10, step_count=st.t)] * 65)
+    b = gs.Batch([gs.Scene(groups=st.groups, n=10, step_count=st.t, schedule=gs.GS_SCHED_DENSE)])
+    with pytest.raises(gs.GsError):
+        b.step(gs.StepConfig(moment_dtype=gs.GS_MOMENT_BF16))
+    b.close()

@@ -1,0 +1,106 @@
+"""Drift of the reduced-precision moment storage against the FP64 oracle.
+
+The 3M-primitive scene is stepped 1000 times on the GPU (visibility from the
+camera rig, RSR every 100 steps with p = 0.05) three ways: FP32 moments,
+BF16 moments rounded to nearest-even, and BF16 moments with stochastic
+rounding.  20 000 sampled primitives are followed by the FP64 oracle on the
+same masks and gradients (the GPU's masks, so boundary flips cannot split the
+trajectories).  After the last step the per-group max and mean unit-floor
+relative error of theta is reported (and written to $GS_REPORT_DIR when set);
+the test bounds them."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+gs = pytest.importorskip("paper_2601_16736_amd")
+from _gpu_util import DEV  # noqa: E402
+
+N, STEPS, SAMPLE = 3_000_000, 1000, 20_000
+LO, LS, CLIP, REG = 1e-3, 1e-5, 10.0, 1e5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+@pytest.fixture(scope="module")
+def scene():
+    sc = synth.scene_uniform(N, seed=0, groups=synth.GROUPS_59)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(0)
+    grads = [[torch.randn((N, d), generator=gen, device=DEV) * 1e-3 for _ in range(4)]
+             for _, d, _, _ in synth.GROUPS_59]
+    rows = np.sort(synth.rng(71).choice(N, SAMPLE, replace=False)).astype(np.int64)
+    return sc, grads, rows
+
+
+def _run(scene, mode):
+    sc, grads, rows = scene
+    spec = synth.GROUPS_59
+    bf16 = mode != "f32"
+    mdt = torch.bfloat16 if bf16 else torch.float32
+    groups = [gs.Group(torch.from_numpy(sc.params[name]).to(DEV), grads[k][0],
+                       torch.zeros((N, d), dtype=mdt, device=DEV), torch.zeros((N, d), dtype=mdt, device=DEV), lr,
+                       dar_kind=dar, dar_lambda=LO if dar == 1 else (LS if dar == 2 else 0.0), dar_clip=CLIP)
+              for k, (name, d, lr, dar) in enumerate(spec)]
+    t = torch.zeros(N, dtype=torch.int32, device=DEV)
+    mask = torch.zeros(N, dtype=torch.uint8, device=DEV)
+    idx = torch.zeros(N, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    rows_t = torch.from_numpy(rows).to(DEV)
+    og = [oracle.Group(sc.params[name][rows].astype(np.float64), np.zeros((SAMPLE, d)), np.zeros((SAMPLE, d)),
+                       np.zeros((SAMPLE, d)), lr, dar_kind=dar, dar_lambda=LO if dar == 1 else (LS if dar == 2 else 0.0),
+                       dar_clip=CLIP) for name, d, lr, dar in spec]
+    ograds = [[gset[rows_t].cpu().numpy().astype(np.float64) for gset in sets] for sets in grads]
+    t_ref = np.zeros(SAMPLE, np.int32)
+    cams = synth.camera_rig()
+    order = synth.camera_order(len(cams), STEPS, seed=0)
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    for k in range(STEPS):
+        gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt)
+        for G, sets in zip(groups, grads):
+            G.grad = sets[k % 4]
+        cfg = gs.StepConfig(reg_norm=REG, seed=0, iteration=k, rsr_enable=(k % 100 == 0), rsr_ratio=0.05,
+                            moment_dtype=int(bf16), stochastic_round=(mode == "bf16_sr"), schedule=1, unit=64)
+        gs.adamw_gs_step(groups, N, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt)
+        m_rows = mask[rows_t].cpu().numpy()
+        for O, gsets in zip(og, ograds):
+            O.grad[:] = gsets[k % 4]
+        oracle.adamw_gs_step(og, SAMPLE, m_rows, t_ref,
+                             oracle.Config(reg_norm=REG, seed=0, iteration=k, rsr_enable=(k % 100 == 0),
+                                           rsr_ratio=0.05), ids=rows)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(t[rows_t].cpu().numpy(), t_ref)
+    report = {}
+    for (name, *_), G, O in zip(spec, groups, og):
+        x = G.param[rows_t].cpu().numpy().astype(np.float64)
+        e = np.abs(x - O.param) / np.maximum(np.abs(O.param), 1.0)
+        report[name] = {"max": float(e.max()), "mean": float(e.mean())}
+    return report
+
+
+def test_moment_precision_drift_1000_steps(scene):
+    rep = {mode: _run(scene, mode) for mode in ("f32", "bf16_rne", "bf16_sr")}
+    out = os.environ.get("GS_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_report.json"), "w") as f:
+            json.dump({"steps": STEPS, "n": N, "sample": SAMPLE, "metric": "|x-r|/max(|r|,1) of theta",
+                       "report": rep}, f, indent=1)
+    print(json.dumps(rep))
+    for name, r in rep["f32"].items():
+        assert r["max"] <= 1e-5, f"FP32 drift of {name}: {r}"
+    for mode in ("bf16_rne", "bf16_sr"):
+        for name, r in rep[mode].items():
+            assert r["max"] <= 0.1, f"{mode} drift of {name}: {r}"
