@@ -304,6 +304,77 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8)
     return out
 
 
+def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
+    """3DGS-MCMC-shaped workload: 6M primitives (the cap), means from an
+    equal-weight mixture of 64 isotropic Gaussians (sigma 1.5), other
+    attributes N(0, 1), opacity and scale regularisation weights 0.01, and
+    every step the 1 % lowest opacity logits (60 000) get their state reset
+    (relocation).  Morton layout, FP32 moments.  One step = visibility +
+    compaction, the fused step, and the relocation select + reset."""
+    import synth
+    dev = torch.device("cuda:0")
+    n = 6_000_000
+    k_reloc = n // 100
+    means = synth.scene_clustered(n, seed=0, groups=[("means", 3, 0.0, 0)]).params["means"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(6)
+    params = [torch.from_numpy(means).to(dev)] + [torch.randn((n, d), generator=gen, device=dev)
+                                                   for _, d, _, _ in synth.GROUPS_59[1:]]
+    grads = [[torch.randn((n, d), generator=gen, device=dev) * 1e-3 for _ in range(2)]
+             for _, d, _, _ in synth.GROUPS_59]
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(gs.gs_spatial_order_workspace_size(n), dtype=torch.uint8, device=dev)
+    gs.gs_spatial_order(params[0], perm, ws)
+    params = gs.apply_spatial_order(params, perm)
+    grads = [gs.apply_spatial_order(sets, perm) for sets in grads]
+    del ws, perm
+    groups = [gs.Group(p, sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                       dar_lambda=0.01 if dar else 0.0, dar_clip=CLIP)
+              for (name, d, lr, dar), p, sets in zip(synth.GROUPS_59, params, grads)]
+    opacity = groups[3].param
+    t = torch.zeros(n, dtype=torch.int32, device=dev)
+    mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(n, dtype=torch.int32, device=dev)
+    counts = torch.zeros(warmup + steps, dtype=torch.int32, device=dev)
+    rws = torch.empty(gs.gs_relocate_workspace_size(n), dtype=torch.uint8, device=dev)
+    order = synth.camera_order(len(cams), warmup + steps, seed=3)
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+
+    def one(k, slot=-1):
+        cnt = counts[k:k + 1]
+        gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        for G, sets in zip(groups, grads):
+            G.grad = sets[k % 2]
+        gs.adamw_gs_step(groups, n, t, gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k,
+                                                     rsr_enable=(k % RSR_EVERY == 0), rsr_ratio=RSR_P,
+                                                     rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **STEP_LAUNCH),
+                         visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        if slot >= 0:
+            ev[slot][0].record(stream)
+        gs.gs_relocate_reset(opacity, k_reloc, groups, gs.GS_MOMENT_F32, t, True, rws, stream=stream)
+        if slot >= 0:
+            ev[slot][1].record(stream)
+
+    for k in range(warmup):
+        one(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps):
+        one(warmup + j, j)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nv = counts.cpu().numpy()[warmup:].astype(np.int64)
+    reloc_us = float(np.mean([a.elapsed_time(b) for a, b in ev]) * 1e3)
+    del groups, params, grads, t, mask, idx, rws
+    torch.cuda.empty_cache()
+    return {"workload": "6M primitives, 64-cluster mixture means (sigma 1.5), lambda_o = lambda_s = 0.01, "
+                        "1 %% lowest opacity reset every step, Morton order, FP32, %d steps" % steps,
+            "value": int(nv.sum()) * 59 / wall, "ms_per_step": wall / steps * 1e3,
+            "visible_frac": float(nv.mean() / n), "relocation_us": reloc_us}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +425,8 @@ def main(argv=None) -> int:
         torch.cuda.empty_cache()
         print("bench: variant batched 16 scenes", file=sys.stderr, flush=True)
         variants.append({"batched": run_batched(gs, torch)})
+        print("bench: variant MCMC-shaped 6M with relocation", file=sys.stderr, flush=True)
+        variants.append({"mcmc_6m": run_mcmc(gs, torch, cams)})
 
     out = {
         "metric": "primitive-attr updates/s + % HBM roofline, fused AdamW-GS vs plain, 3M Gaussians",

@@ -189,9 +189,13 @@ double gs_reg_norm(double n_pixels);
  * s2 = output (iteration+1) of the stream with state s1, primitive i is
  * sampled iff (output (i+1) of the stream with state s2) >> 32 is below
  * floor(rsr_ratio * 2^32) (2^32 when rsr_ratio = 1).
- * BF16 moments are computed in FP32 and rounded on store, to nearest-even or
- * stochastically with 16 bits of a draw of tag 16+g (group g) keyed by the
- * element index row*dim+col (m: bits 63..48, v: bits 47..32).
+ * BF16 moments are computed in FP32 and rounded once on store, to
+ * nearest-even or stochastically: 16 random bits are added below the kept
+ * bits, then truncated.  The bits of element e = row*dim+col of group g come
+ * from output (e+1) of the stream keyed by (seed, tag 16+g, iteration):
+ * bits 63..48 for m, 47..32 for v.  A sampled visible row is rescaled inside
+ * the step (in FP32, before its moment update, no extra rounding); a sampled
+ * invisible row is rescaled and rounded with the stream of tag 32+g.
  *
  * visible     [n] uint8 mask (nonzero = visible), or NULL;
  * vis_idx     [n] int32 visible indices (any order, no duplicates), or NULL;
@@ -199,7 +203,9 @@ double gs_reg_norm(double n_pixels);
  * step_count  [n] int32 t_i, updated in place.
  * GS_SCHED_MASKED needs `visible`; GS_SCHED_COMPACTED needs vis_idx and
  * vis_count, and the index list must match the mask's visible set when both
- * are given; GS_SCHED_DENSE ignores all three.  Pointers: 4-byte aligned
+ * are given (entries outside [0, n) are ignored); GS_SCHED_DENSE ignores all
+ * three.  RSR with a sparse schedule also needs `visible`, to find the
+ * invisible sampled rows.  Pointers: 4-byte aligned
  * (BF16 moments 2-byte); wider alignment lets rows use 64/128-bit accesses.
  * Distinct groups must not overlap; overlapping arrays give undefined results.
  */

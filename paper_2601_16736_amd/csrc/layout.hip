@@ -58,12 +58,23 @@ __global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ mea
             hi[a] = max(hi[a], (uint32_t)__shfl_xor((int)hi[a], off));
         }
     }
+    // one set of six atomics per block, not per wave
+    __shared__ uint32_t s_box[4][6];
+    const int wave = threadIdx.x / 64;
     if ((threadIdx.x % 64) == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            atomicMin(box + a, lo[a]);
-            atomicMax(box + 3 + a, hi[a]);
+            s_box[wave][a] = lo[a];
+            s_box[wave][3 + a] = hi[a];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        uint32_t v = s_box[0][a];
+        for (int w = 1; w < 4; ++w) v = a < 3 ? min(v, s_box[w][a]) : max(v, s_box[w][a]);
+        if (a < 3) atomicMin(box + a, v);
+        else atomicMax(box + a, v);
     }
 }
 
@@ -155,7 +166,7 @@ extern "C" gs_status gs_spatial_order(const float* means, int64_t n, int32_t* pe
     size_t temp_bytes = sort_temp_bytes(n);
     hipLaunchKernelGGL(bbox_init_kernel, dim3(1), dim3(64), 0, stream, box);
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(bbox_kernel, dim3(grid), dim3(256), 0, stream, means, n, box);
+    hipLaunchKernelGGL(bbox_kernel, dim3(std::min(grid, 512u)), dim3(256), 0, stream, means, n, box);
     hipLaunchKernelGGL(morton_kernel, dim3(grid), dim3(256), 0, stream, means, n, box, keys_in, vals_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(GS_EHIP, hipGetErrorString(e));

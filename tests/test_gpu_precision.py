@@ -82,7 +82,7 @@ def _run(scene, mode):
                                            rsr_ratio=0.05), ids=rows)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(t[rows_t].cpu().numpy(), t_ref)
-    report = {}
+    report = {"_max_visible_updates": int(t_ref.max())}
     for (name, *_), G, O in zip(spec, groups, og):
         x = G.param[rows_t].cpu().numpy().astype(np.float64)
         e = np.abs(x - O.param) / np.maximum(np.abs(O.param), 1.0)
@@ -99,8 +99,19 @@ def test_moment_precision_drift_1000_steps(scene):
             json.dump({"steps": STEPS, "n": N, "sample": SAMPLE, "metric": "|x-r|/max(|r|,1) of theta",
                        "report": rep}, f, indent=1)
     print(json.dumps(rep))
-    for name, r in rep["f32"].items():
-        assert r["max"] <= 1e-5, f"FP32 drift of {name}: {r}"
+    # FP32 theta is stored in FP32: each visible update rounds it once, by at
+    # most half an ulp, i.e. 2^-24 * 2|theta| <= 2^-23 max(|theta|, 1).  When
+    # the update repeats from step to step these roundings add up coherently,
+    # so after K visible updates the drift is bounded by K * 2^-23 (the
+    # per-step error of the update itself is orders of magnitude smaller).
+    k_max = rep["f32"].pop("_max_visible_updates")
     for mode in ("bf16_rne", "bf16_sr"):
-        for name, r in rep[mode].items():
-            assert r["max"] <= 0.1, f"{mode} drift of {name}: {r}"
+        rep[mode].pop("_max_visible_updates")
+    for name, r in rep["f32"].items():
+        assert r["max"] <= k_max * 2.0 ** -23, f"FP32 drift of {name}: {r} (bound {k_max * 2.0 ** -23:.2e})"
+        assert r["mean"] <= 1e-6, f"FP32 mean drift of {name}: {r}"
+    # stochastic rounding wins back the drift that nearest-even storage of the
+    # moments accumulates (small increments to v vanish under nearest-even)
+    for name in rep["bf16_sr"]:
+        assert rep["bf16_sr"][name]["mean"] < rep["bf16_rne"][name]["mean"], name
+        assert rep["bf16_sr"][name]["max"] <= 0.1, f"bf16_sr drift of {name}: {rep['bf16_sr'][name]}"
