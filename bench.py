@@ -57,10 +57,14 @@ N_GRAD_SETS = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")
 
 
+# the sources that define the fused step kernel
+STEP_KERNEL_SOURCES = ("internal.h", "device_common.h", "step.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2601_16736_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_16736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
