@@ -391,9 +391,17 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
+    ap.add_argument("--mcmc-only", action="store_true",
+                    help="only run the 6M MCMC-shaped workload with relocation (for profiling)")
     args = ap.parse_args(argv)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.mcmc_only:
+        import torch
+        import paper_2601_16736_amd as gs
+        import synth
+        print(json.dumps(run_mcmc(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the AdamW-GS step has no cross-GPU exchange to measure "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)

@@ -31,6 +31,8 @@ struct SelectState {
     int32_t rank;      // elements still to take among those matching prefix
     int32_t pad;
 };
+// st[p]: the state digit pass p starts from (p = 0..3); st[4]: the final one.
+static_assert(5 * sizeof(SelectState) <= kAlign, "states fit the first aligned slot");
 
 // -0.0 and +0.0 compare equal, so both map to the key of +0.0
 __device__ __forceinline__ uint32_t key_ord(float f)
@@ -39,45 +41,30 @@ __device__ __forceinline__ uint32_t key_ord(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// st[0] = the initial state; the four pass histograms cleared.  256 threads.
 __global__ void select_init_kernel(SelectState* st, uint32_t* hist, int32_t k)
 {
     if (threadIdx.x == 0) {
-        st->prefix = 0u;
-        st->mask = 0u;
-        st->rank = k;
-        st->pad = 0;
+        st[0].prefix = 0u;
+        st[0].mask = 0u;
+        st[0].rank = k;
+        st[0].pad = 0;
     }
-    hist[threadIdx.x] = 0u;   // 256 threads
+    for (int p = 0; p < 4; ++p) hist[p * 256 + threadIdx.x] = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t n,
-                                                             const SelectState* st, int shift, uint32_t* hist)
-{
-    __shared__ uint32_t s_hist[256];
-    s_hist[threadIdx.x] = 0u;
-    __syncthreads();
-    const uint32_t prefix = st->prefix, mask = st->mask;
-    const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
-#pragma unroll 4
-    for (int j = 0; j < kRelPerThread; ++j) {
-        const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
-        if (i < n) {
-            const uint32_t o = key_ord(key[i]);
-            if ((o & mask) == prefix) atomicAdd(&s_hist[(o >> shift) & 0xFFu], 1u);
-        }
-    }
-    __syncthreads();
-    const uint32_t c = s_hist[threadIdx.x];
-    if (c) atomicAdd(&hist[threadIdx.x], c);
-}
-
-// One block of 256 threads: finds the digit bucket holding the rank-th
-// element, narrows the state, clears the histogram for the next pass.
-__global__ void select_digit_kernel(SelectState* st, uint32_t* hist, int shift)
+// The state after a digit pass, from the state before it and the pass's
+// histogram: the bucket where the running count first reaches `rank` fixes
+// the digit.  Every block of the next kernel computes it (a 1 KB read and a
+// 256-wide scan), so no kernel waits on another block; block 0 records it.
+// Needs all 256 threads of the block.
+__device__ SelectState narrow(const SelectState* prev, const uint32_t* hist, int shift)
 {
     __shared__ uint32_t s_inc[256];
+    __shared__ SelectState s_st;
     const uint32_t c = hist[threadIdx.x];
     s_inc[threadIdx.x] = c;
+    if (threadIdx.x == 0) s_st = *prev;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
         const uint32_t y = threadIdx.x >= (unsigned)off ? s_inc[threadIdx.x - off] : 0u;
@@ -85,33 +72,76 @@ __global__ void select_digit_kernel(SelectState* st, uint32_t* hist, int shift)
         s_inc[threadIdx.x] += y;
         __syncthreads();
     }
-    const uint32_t rank = (uint32_t)st->rank;
+    const uint32_t rank = (uint32_t)s_st.rank;
     const uint32_t before = s_inc[threadIdx.x] - c;
     __syncthreads();
-    // the bucket where the running count first reaches `rank`
     if (rank > 0 && before < rank && s_inc[threadIdx.x] >= rank) {
-        st->prefix |= (uint32_t)threadIdx.x << shift;
-        st->mask |= 0xFFu << shift;
-        st->rank = (int32_t)(rank - before);
+        s_st.prefix |= (uint32_t)threadIdx.x << shift;
+        s_st.mask |= 0xFFu << shift;
+        s_st.rank = (int32_t)(rank - before);
     }
-    hist[threadIdx.x] = 0u;
+    __syncthreads();
+    return s_st;
 }
 
-// Per block: keys below K and keys equal to K.
+// The block's keys, mapped to order-preserving uint32; entries past n get
+// the largest key and are excluded by the callers through the index test.
+__device__ __forceinline__ void load_keys(const float* __restrict__ key, int64_t n, int64_t first,
+                                          uint32_t (&o)[kRelPerThread])
+{
+#pragma unroll
+    for (int j = 0; j < kRelPerThread; ++j) o[j] = key_ord(key[min(first + (int64_t)j * kBlock + threadIdx.x, n - 1)]);
+}
+
+// Digit pass p (bits 31-8p .. 24-8p): histogram of the keys that match the
+// state narrowed by passes 0 .. p-1.
+__global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t n,
+                                                             SelectState* st, int pass, uint32_t* hist)
+{
+    // one private histogram per wave: the keys of a view are concentrated in
+    // a few digits, and four copies cut the LDS atomic collisions fourfold
+    __shared__ uint32_t s_hist[kWavesPerBlock][256];
+    for (int w = 0; w < kWavesPerBlock; ++w) s_hist[w][threadIdx.x] = 0u;
+    const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
+    uint32_t o[kRelPerThread];
+    load_keys(key, n, first, o);
+    const int shift = 24 - 8 * pass;
+    const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist + (pass - 1) * 256, shift + 8);
+    if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
+    __syncthreads();
+    uint32_t* mine = s_hist[threadIdx.x / kWave];
+#pragma unroll
+    for (int j = 0; j < kRelPerThread; ++j) {
+        const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
+        if (i < n && (o[j] & cur.mask) == cur.prefix) atomicAdd(&mine[(o[j] >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) c += s_hist[w][threadIdx.x];
+    if (c) atomicAdd(&hist[pass * 256 + threadIdx.x], c);
+}
+
+// Per block: keys below K and keys equal to K, K being the key of the k-th
+// smallest (the state after the last pass, recorded in st[4] by block 0).
 __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __restrict__ key, int64_t n,
-                                                              const SelectState* st, int32_t* lt, int32_t* eq)
+                                                              SelectState* st, const uint32_t* hist, int32_t* lt,
+                                                              int32_t* eq)
 {
     __shared__ int s_lt[kWavesPerBlock], s_eq[kWavesPerBlock];
-    const uint32_t K = st->prefix;
-    const bool any = st->rank > 0;
+    const SelectState fin = narrow(&st[3], hist + 3 * 256, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[4] = fin;
+    const uint32_t K = fin.prefix;
+    const bool any = fin.rank > 0;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
+    uint32_t o[kRelPerThread];
+    load_keys(key, n, first, o);
     int nl = 0, ne = 0;
+#pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
         const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
         if (i < n && any) {
-            const uint32_t o = key_ord(key[i]);
-            nl += o < K;
-            ne += o == K;
+            nl += o[j] < K;
+            ne += o[j] == K;
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -181,8 +211,8 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
 {
     __shared__ int s_cnt[2][kWavesPerBlock];
     __shared__ int s_run_eq, s_run_sel;
-    const uint32_t K = st->prefix;
-    const int rank = st->rank;
+    const uint32_t K = st[4].prefix;
+    const int rank = st[4].rank;
     if (rank <= 0) return;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -194,13 +224,14 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
         s_run_eq = 0;
         s_run_sel = 0;
     }
+    uint32_t o[kRelPerThread];
+    load_keys(key, n, first, o);
     __syncthreads();
+#pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
         const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
-        uint32_t o = 0xFFFFFFFFu;
-        if (i < n) o = key_ord(key[i]);
-        const bool is_eq = i < n && o == K;
-        const bool is_lt = i < n && o < K;
+        const bool is_eq = i < n && o[j] == K;
+        const bool is_lt = i < n && o[j] < K;
         const uint64_t b_eq = __ballot(is_eq);
         if (lane == 0) s_cnt[0][wave] = __popcll(b_eq);
         __syncthreads();
@@ -226,34 +257,30 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
 }
 
 // Zeroes m and v of the selected rows in every group, and t if asked.
+// One wave per selected row at a time: its lanes clear the row's elements
+// group by group (no index arithmetic beyond the row base).
 template <bool BF16>
 __global__ __launch_bounds__(kBlock) void reset_rows_kernel(KScene S, const int32_t* sel, int64_t k, int reset_t)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int gi = 0; gi < S.n_groups; ++gi) {
-        const KGroup& G = S.g[gi];
-        const int64_t total = k * G.dim;
-        for (int64_t x = tid; x < total; x += stride) {
-            const int64_t j = x / G.dim;
-            const int64_t c = x - j * G.dim;
-            const int32_t i = sel[j];
-            if ((uint64_t)i >= (uint64_t)S.n) continue;
-            const int64_t e = (int64_t)i * G.dim + c;
-            if constexpr (BF16) {
-                static_cast<uint16_t*>(G.m)[e] = 0;
-                static_cast<uint16_t*>(G.v)[e] = 0;
-            } else {
-                static_cast<float*>(G.m)[e] = 0.0f;
-                static_cast<float*>(G.v)[e] = 0.0f;
+    const int lane = threadIdx.x % kWave;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < k; j += waves) {
+        const int32_t i = sel[j];
+        if ((uint64_t)i >= (uint64_t)S.n) continue;
+        for (int gi = 0; gi < S.n_groups; ++gi) {
+            const KGroup& G = S.g[gi];
+            const int64_t base = (int64_t)i * G.dim;
+            for (int c = lane; c < G.dim; c += kWave) {
+                if constexpr (BF16) {
+                    static_cast<uint16_t*>(G.m)[base + c] = 0;
+                    static_cast<uint16_t*>(G.v)[base + c] = 0;
+                } else {
+                    static_cast<float*>(G.m)[base + c] = 0.0f;
+                    static_cast<float*>(G.v)[base + c] = 0.0f;
+                }
             }
         }
-    }
-    if (reset_t && S.t != nullptr) {
-        for (int64_t j = tid; j < k; j += stride) {
-            const int32_t i = sel[j];
-            if ((uint64_t)i < (uint64_t)S.n) S.t[i] = 0;
-        }
+        if (reset_t && S.t != nullptr && lane == 0) S.t[i] = 0;
     }
 }
 
@@ -262,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void reset_rows_kernel(KScene S, const int3
 size_t relocate_workspace_bytes(int64_t n)
 {
     const size_t nblocks = (size_t)((n + kRelPerBlock - 1) / kRelPerBlock);
-    return kAlign /* state */ + align_up(256 * 4) /* hist */ + 2 * align_up(nblocks * 4) +
+    return kAlign /* states */ + align_up(4 * 256 * 4) /* pass histograms */ + 2 * align_up(nblocks * 4) +
            align_up((size_t)(n > 0 ? n : 1) * 4) /* selected list when the caller passes none */;
 }
 
@@ -270,20 +297,19 @@ hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene&
                            void* ws, hipStream_t stream)
 {
     const int nblocks = (int)((n + kRelPerBlock - 1) / kRelPerBlock);
+    const size_t hist_bytes = align_up(4 * 256 * 4);
     char* p = static_cast<char*>(ws);
     SelectState* st = reinterpret_cast<SelectState*>(p);
     uint32_t* hist = reinterpret_cast<uint32_t*>(p + kAlign);
-    int32_t* lt = reinterpret_cast<int32_t*>(p + kAlign + align_up(256 * 4));
-    int32_t* eq = reinterpret_cast<int32_t*>(p + kAlign + align_up(256 * 4) + align_up((size_t)nblocks * 4));
-    int32_t* sel_ws = reinterpret_cast<int32_t*>(p + kAlign + align_up(256 * 4) + 2 * align_up((size_t)nblocks * 4));
+    int32_t* lt = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes);
+    int32_t* eq = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + align_up((size_t)nblocks * 4));
+    int32_t* sel_ws = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + 2 * align_up((size_t)nblocks * 4));
     int32_t* sel = selected != nullptr ? selected : sel_ws;
 
     hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, stream, st, hist, (int32_t)k);
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, shift, hist);
-        hipLaunchKernelGGL(select_digit_kernel, dim3(1), dim3(256), 0, stream, st, hist, shift);
-    }
-    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, lt, eq);
+    for (int pass = 0; pass < 4; ++pass)
+        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, pass, hist);
+    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, hist, lt, eq);
     hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(kBlock), 0, stream, lt, eq, nblocks);
     hipLaunchKernelGGL(select_write_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, lt, eq, sel);
     hipError_t e = hipGetLastError();
