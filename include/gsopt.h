@@ -160,6 +160,33 @@ typedef struct {
     double rsr_ratio;        /* sampling probability p in [0, 1] */
     float visible_hint;      /* expected visible fraction for GS_SCHED_AUTO (<= 0: unknown) */
     int32_t unit;            /* rows (compacted) / primitives (masked, dense) per wave; 0 = default */
+    /* Position noise (Implementation Details, position equations): each
+     * visible primitive's mean also moves by -eta_{R_o} R_mu, R_mu =
+     * eta_mu sigma(-lambda_mu (sigma(tau) - lambda_t)) Sigma gamma, with
+     * Sigma = R(q) diag(exp(2 kappa)) R(q)^T from the pre-update quaternion
+     * q = (w, x, y, z) (normalised) and log-scale kappa, tau the pre-update
+     * opacity logit, eta_mu the mean group's lr, and gamma ~ N(0, I3) by the
+     * Box-Muller transform of two draws d1, d2 (outputs 2i+1, 2i+2 of the
+     * stream keyed by (seed, tag 48, iteration)): u = (top 24 bits + 1)/2^24,
+     * a = (bits 31..8)/2^24, gamma = (r1 cos 2 pi a1, r1 sin 2 pi a1,
+     * r2 cos 2 pi a2), r = sqrt(-2 ln u).  The paper takes lambda_mu,
+     * lambda_t and eta_{R_o} from 3DGS-MCMC without printing them. */
+    int32_t noise_enable;    /* 1 = on */
+    int32_t noise_groups[4]; /* group indices of the mean (dim 3), log-scale (dim 3),
+                                quaternion (dim 4) and opacity logit (dim 1) */
+    double noise_lr;         /* eta_{R_o} >= 0 */
+    double noise_k;          /* lambda_mu */
+    double noise_t;          /* lambda_t */
+    /* Artificial Implicit Update (Sec. "Update-step decoupling", AIU): each
+     * invisible primitive is sampled with probability aiu_ratio (Pro_AIU) by
+     * the Re-State rule on stream tag 64, and a sampled one with t_i > 0
+     * takes theta <- theta - lr aiu_scale (m/b1)/(sqrt(v/b2) + eps) from its
+     * moments after this call's Re-State rescale, with b1, b2 from its
+     * current t_i; m, v and t_i stay unchanged, and no regulariser term is
+     * added.  The paper's comparison tool; AdamW-GS itself runs without it. */
+    int32_t aiu_enable;      /* 1 = on */
+    double aiu_ratio;        /* Pro_AIU in [0, 1] */
+    double aiu_scale;        /* eta_AIU >= 0 */
 } gs_step_config;
 
 /*
@@ -182,7 +209,9 @@ double gs_reg_norm(double n_pixels);
  *     d = sqrt(v/b2) + eps;  u = (m/b1)/d;
  *     DAR groups add min(lambda R'(theta)/N_I'/d, C) (or the reg_mode
  *     variant), with R' at the pre-update theta;
- *     theta <- theta - lr u.
+ *     theta <- theta - lr u;
+ *  5. with position noise on, visible means also move by -eta_{R_o} R_mu;
+ *  6. with AIU on, sampled invisible rows move as stated at aiu_enable.
  * Sampling: the k-th output of a SplitMix64 stream with state s is
  * mix64(s + k*0x9E3779B97F4A7C15) (Steele, Lea & Flood 2014).  With
  * s1 = output (1+1) of the stream seeded with `seed` (tag 1) and
@@ -204,8 +233,8 @@ double gs_reg_norm(double n_pixels);
  * GS_SCHED_MASKED needs `visible`; GS_SCHED_COMPACTED needs vis_idx and
  * vis_count, and the index list must match the mask's visible set when both
  * are given (entries outside [0, n) are ignored); GS_SCHED_DENSE ignores all
- * three.  RSR with a sparse schedule also needs `visible`, to find the
- * invisible sampled rows.  Pointers: 4-byte aligned
+ * three.  RSR or AIU with a sparse schedule also needs `visible`, to find
+ * the invisible sampled rows.  Pointers: 4-byte aligned
  * (BF16 moments 2-byte); wider alignment lets rows use 64/128-bit accesses.
  * Distinct groups must not overlap; overlapping arrays give undefined results.
  */
@@ -332,6 +361,45 @@ gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* w
  */
 gs_status gs_gather_rows(const void* src, void* dst, const int32_t* perm, int64_t n,
                          int64_t row_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Primitive-set mutation around the step.  Densification removes primitives
+ * and generates new ones (Sec. "Preliminaries"; Optimization paragraph of
+ * the appendix); a newly generated primitive's optimizer state is that of
+ * RSR with alpha1 = alpha2 = 0 ("Scaling in RSR", Sec. "Hyperparameter
+ * Selection").  The policy that decides what to prune or clone, and how a
+ * clone is then moved or rescaled, is the caller's.  Gradients are not
+ * carried: they belong to one iteration.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace gs_prune needs for n primitives (0 for n = 0). */
+size_t gs_prune_workspace_size(int64_t n);
+
+/*
+ * Pruning: the rows i with keep[i] != 0, in ascending order, are copied with
+ * their theta, m, v (each group of src to the same group of dst) and t_src[i]
+ * to the front of the destination arrays; *kept_count (a device int32)
+ * receives their number.  Out of place: no dst array may overlap a src
+ * array.  The destination arrays must hold as many rows as will be kept (n
+ * is always enough); rows beyond the kept count are not written.
+ * keep [n] uint8; t_src, t_dst [n] int32; group dims equal in src and dst;
+ * the grad pointers are ignored (may be NULL).  workspace:
+ * gs_prune_workspace_size(n) bytes (any alignment; 256 bytes of it are slack
+ * for alignment), used only during the call's kernels.
+ */
+gs_status gs_prune(const uint8_t* keep, int64_t n, const gs_group* src, const gs_group* dst,
+                   int32_t n_groups, int32_t moment_dtype, const int32_t* t_src, int32_t* t_dst,
+                   int32_t* kept_count, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * New primitives: for j in [0, k), row n + j of every group takes theta of
+ * row src_idx[j] (a clone) and a fresh state, m = v = 0 and step_count = 0.
+ * The arrays must hold n + k rows; rows below n do not change.  src_idx [k]
+ * int32 (device); an entry outside [0, n) leaves that new row's theta as it
+ * was (its state is still cleared).  The grad pointers are ignored.
+ */
+gs_status gs_append(const gs_group* groups, int32_t n_groups, int32_t moment_dtype, int64_t n,
+                    const int32_t* src_idx, int64_t k, int32_t* step_count, hipStream_t stream);
 
 #ifdef __cplusplus
 }

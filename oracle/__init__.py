@@ -61,7 +61,10 @@ class _Config(ctypes.Structure):
                 ("reg_norm", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("iteration", ctypes.c_int64), ("rsr_enable", ctypes.c_int32),
                 ("rsr_alpha1", ctypes.c_double), ("rsr_alpha2", ctypes.c_double),
-                ("rsr_ratio", ctypes.c_double)]
+                ("rsr_ratio", ctypes.c_double), ("noise_enable", ctypes.c_int32),
+                ("noise_groups", ctypes.c_int32 * 4), ("noise_lr", ctypes.c_double),
+                ("noise_k", ctypes.c_double), ("noise_t", ctypes.c_double),
+                ("aiu_enable", ctypes.c_int32), ("aiu_ratio", ctypes.c_double), ("aiu_scale", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +85,8 @@ def lib():
         L.orc_rsr_sampled.restype = ctypes.c_int; L.orc_rsr_sampled.argtypes = [u64, i64, i64, ctypes.c_double]
         L.orc_rsr_sample_mask.restype = None
         L.orc_rsr_sample_mask.argtypes = [u64, i64, vp, i64, ctypes.c_double, vp]
+        L.orc_aiu_sample_mask.restype = None
+        L.orc_aiu_sample_mask.argtypes = [u64, i64, vp, i64, ctypes.c_double, vp]
         L.orc_reg_norm.restype = ctypes.c_double; L.orc_reg_norm.argtypes = [ctypes.c_double]
         L.orc_visible_f32.restype = ctypes.c_int; L.orc_visible_f32.argtypes = [vp, vp, vp]
         L.orc_visibility.restype = None; L.orc_visibility.argtypes = [vp, vp, i64, vp, vp]
@@ -90,8 +95,13 @@ def lib():
         L.orc_adamw_gs_step.restype = None; L.orc_adamw_gs_step.argtypes = [vp, i32, i64, vp, vp, vp]
         L.orc_adamw_gs_step_rows.restype = None
         L.orc_adamw_gs_step_rows.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+        L.orc_noise_gamma.restype = None; L.orc_noise_gamma.argtypes = [u64, i64, i64, vp]
+        L.orc_noise_displacement.restype = None
+        L.orc_noise_displacement.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
         L.orc_select_smallest.restype = None; L.orc_select_smallest.argtypes = [vp, i64, i64, vp]
         L.orc_reset_state.restype = None; L.orc_reset_state.argtypes = [vp, i32, vp, i64, vp, i32]
+        L.orc_prune.restype = i64; L.orc_prune.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+        L.orc_append.restype = None; L.orc_append.argtypes = [vp, i32, i64, vp, i64, vp]
         L.orc_bf16_rne.restype = ctypes.c_uint16; L.orc_bf16_rne.argtypes = [ctypes.c_float]
         L.orc_bf16_sr.restype = ctypes.c_uint16; L.orc_bf16_sr.argtypes = [ctypes.c_float, ctypes.c_uint32]
         _lib = L
@@ -143,6 +153,17 @@ def rsr_sample_mask(seed: int, iteration: int, n: int, ratio: float,
         n = ids.shape[0]
     out = np.zeros(n, np.uint8)
     lib().orc_rsr_sample_mask(seed & (2**64 - 1), iteration, _ptr(ids), n, float(ratio), _ptr(out))
+    return out.astype(bool)
+
+
+def aiu_sample_mask(seed: int, iteration: int, n: int, ratio: float,
+                    ids: Optional[np.ndarray] = None) -> np.ndarray:
+    """AIU sample flags (bool) of primitives 0..n-1, or of ``ids``."""
+    if ids is not None:
+        ids = _need(np.ascontiguousarray(ids), np.int64)
+        n = ids.shape[0]
+    out = np.zeros(n, np.uint8)
+    lib().orc_aiu_sample_mask(seed & (2**64 - 1), iteration, _ptr(ids), n, float(ratio), _ptr(out))
     return out.astype(bool)
 
 
@@ -241,6 +262,14 @@ class Config:
     rsr_alpha1: float = 0.2
     rsr_alpha2: float = 0.04
     rsr_ratio: float = 0.0
+    noise_enable: bool = False
+    noise_groups: tuple = (0, 1, 2, 3)     # mean, log-scale, quaternion, opacity-logit groups
+    noise_lr: float = 0.0                  # eta_{R_o}
+    noise_k: float = 100.0                 # lambda_mu
+    noise_t: float = 0.005                 # lambda_t
+    aiu_enable: bool = False
+    aiu_ratio: float = 0.0                 # Pro_AIU
+    aiu_scale: float = 0.0                 # eta_AIU
 
 
 def _groups_struct(groups: List[Group]):
@@ -267,7 +296,32 @@ def _config_struct(cfg: Config) -> _Config:
     c.iteration = cfg.iteration
     c.rsr_enable = int(bool(cfg.rsr_enable))
     c.rsr_alpha1, c.rsr_alpha2, c.rsr_ratio = cfg.rsr_alpha1, cfg.rsr_alpha2, cfg.rsr_ratio
+    c.noise_enable = int(bool(cfg.noise_enable))
+    for k in range(4):
+        c.noise_groups[k] = int(cfg.noise_groups[k])
+    c.noise_lr, c.noise_k, c.noise_t = cfg.noise_lr, cfg.noise_k, cfg.noise_t
+    c.aiu_enable = int(bool(cfg.aiu_enable))
+    c.aiu_ratio, c.aiu_scale = cfg.aiu_ratio, cfg.aiu_scale
     return c
+
+
+def noise_gamma(seed: int, iteration: int, i: int) -> np.ndarray:
+    """gamma ~ N(0, I3) of primitive i (Box-Muller on the counter draws)."""
+    g = np.zeros(3)
+    lib().orc_noise_gamma(seed & (2**64 - 1), iteration, i, _ptr(g))
+    return g
+
+
+def noise_displacement(q, kappa, tau: float, lr_mu: float, cfg: Config, gamma) -> np.ndarray:
+    """eta_{R_o} R_mu of one primitive (position equations, Implementation Details)."""
+    q = np.ascontiguousarray(q, np.float64)
+    kappa = np.ascontiguousarray(kappa, np.float64)
+    gamma = np.ascontiguousarray(gamma, np.float64)
+    out = np.zeros(3)
+    c = _config_struct(cfg)
+    lib().orc_noise_displacement(_ptr(q), _ptr(kappa), float(tau), float(lr_mu), ctypes.addressof(c), _ptr(gamma),
+                                 _ptr(out))
+    return out
 
 
 def adamw_gs_step(groups: List[Group], n: int, visible: Optional[np.ndarray], t: np.ndarray,
@@ -306,6 +360,39 @@ def reset_state(groups: List[Group], sel: np.ndarray, t: Optional[np.ndarray], r
     arr = _groups_struct(groups)
     lib().orc_reset_state(ctypes.addressof(arr), len(groups), _ptr(sel), sel.shape[0], _ptr(t),
                           int(bool(reset_t)))
+
+
+def prune(src: List[Group], keep: np.ndarray, t: np.ndarray):
+    """Order-preserving compaction of theta, m, v and t by ``keep``; returns
+    (groups of the kept rows, their step counts)."""
+    keep = _need(np.ascontiguousarray(keep), np.uint8)
+    _need(t, np.int32)
+    n = keep.shape[0]
+    k = int(np.count_nonzero(keep))
+    dst = [Group(np.zeros((max(k, 1), g.dim)), np.zeros((max(k, 1), g.dim)), np.zeros((max(k, 1), g.dim)),
+                 np.zeros((max(k, 1), g.dim)), g.lr, g.dar_kind, g.dar_lambda, g.dar_clip, g.reg_mode) for g in src]
+    t_dst = np.zeros(max(k, 1), np.int32)
+    a, b = _groups_struct(src), _groups_struct(dst)
+    w = lib().orc_prune(ctypes.addressof(a), ctypes.addressof(b), len(src), n, _ptr(keep), _ptr(t), _ptr(t_dst))
+    assert w == k
+    for g in dst:
+        g.param, g.grad, g.m, g.v = g.param[:k], g.grad[:k], g.m[:k], g.v[:k]
+    return dst, t_dst[:k]
+
+
+def append(groups: List[Group], n: int, src_idx: np.ndarray, t: np.ndarray) -> None:
+    """Rows n .. n+k-1 (the arrays hold at least n+k rows) become clones of
+    rows src_idx with zero state, in place."""
+    src_idx = _need(np.ascontiguousarray(src_idx), np.int64)
+    _need(t, np.int32)
+    k = src_idx.shape[0]
+    for g in groups:
+        if g.param.shape[0] < n + k or t.shape[0] < n + k:
+            raise ValueError("arrays must hold n + k rows")
+        if k and (src_idx.min() < 0 or src_idx.max() >= n):
+            raise ValueError("source rows must be below n")
+    arr = _groups_struct(groups)
+    lib().orc_append(ctypes.addressof(arr), len(groups), n, _ptr(src_idx), k, _ptr(t))
 
 
 def bf16_rne(x: float) -> int:

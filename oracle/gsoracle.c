@@ -91,6 +91,18 @@ void orc_rsr_sample_mask(uint64_t seed, int64_t iteration, const int64_t* ids, i
         out[k] = (uint8_t)orc_rsr_sampled(seed, iteration, ids ? ids[k] : k, ratio);
 }
 
+/* AIU sample flags (Sec. "Update-step decoupling", AIU): the same uniform,
+ * independent Bernoulli sampler as the Re-State sample, on stream tag 64.
+ * Only invisible primitives act on the flag. */
+void orc_aiu_sample_mask(uint64_t seed, int64_t iteration, const int64_t* ids, int64_t n,
+                         double ratio, uint8_t* out)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        uint64_t u = orc_draw(seed, 64ULL, iteration, (uint64_t)(ids ? ids[k] : k)) >> 32;
+        out[k] = (uint8_t)(u < orc_rsr_threshold(ratio));
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* DAR pixel-count normaliser (Sec. "Hyperparameter Selection", DAR          */
 /* paragraph): keep only the most significant decimal digit of N_I, then     */
@@ -224,7 +236,79 @@ typedef struct {
     int64_t iteration;
     int32_t rsr_enable;
     double rsr_alpha1, rsr_alpha2, rsr_ratio;
+    /* position noise (Implementation Details, position equations) */
+    int32_t noise_enable;
+    int32_t noise_groups[4];   /* indices of the mean, log-scale, quaternion, opacity-logit groups */
+    double noise_lr;           /* eta_{R_o} */
+    double noise_k, noise_t;   /* lambda_mu, lambda_t */
+    /* Artificial Implicit Update (Sec. "Update-step decoupling", AIU) */
+    int32_t aiu_enable;
+    double aiu_ratio;          /* Pro_AIU: sampling probability of an invisible primitive */
+    double aiu_scale;          /* eta_AIU: scale of the extra update */
 } orc_config;
+
+#define ORC_TAG_AIU 64ULL
+
+#define ORC_TAG_NOISE 48ULL
+
+/*
+ * gamma ~ N(0, I_3) of primitive i by the Box-Muller transform (Box &
+ * Muller 1958) of four 24-bit uniforms taken from two draws of the stream
+ * (seed, tag 48, iteration): d1 = output (2i+1), d2 = output (2i+2);
+ * u_k = (top 24 bits of d_k + 1) / 2^24 in (0, 1], a_k = (bits 31..8 of d_k)
+ * / 2^24 in [0, 1).  gamma = (r1 cos 2 pi a1, r1 sin 2 pi a1, r2 cos 2 pi a2),
+ * r_k = sqrt(-2 ln u_k).
+ */
+void orc_noise_gamma(uint64_t seed, int64_t iteration, int64_t i, double* g)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t s = orc_stream_state(seed, ORC_TAG_NOISE, iteration);
+    uint64_t d1 = orc_splitmix_output(s, 2 * (uint64_t)i + 1);
+    uint64_t d2 = orc_splitmix_output(s, 2 * (uint64_t)i + 2);
+    double u1 = (double)((d1 >> 40) + 1) / 16777216.0;
+    double a1 = (double)((d1 >> 8) & 0xFFFFFFULL) / 16777216.0;
+    double u2 = (double)((d2 >> 40) + 1) / 16777216.0;
+    double a2 = (double)((d2 >> 8) & 0xFFFFFFULL) / 16777216.0;
+    double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u2));
+    g[0] = r1 * cos(two_pi * a1);
+    g[1] = r1 * sin(two_pi * a1);
+    g[2] = r2 * cos(two_pi * a2);
+}
+
+/*
+ * Position noise displacement (Implementation Details, position equations):
+ * R_mu = eta_mu * sigma(-lambda_mu (o - lambda_t)) * Sigma gamma, added to the
+ * mean's update with weight eta_{R_o} / eta_mu inside the bracket that eta_mu
+ * multiplies, i.e. mu moves by -eta_{R_o} * R_mu.  o = sigma(tau) is the
+ * opacity, Sigma = R(q) S S^T R(q)^T with S = diag(exp(kappa)) and R(q) the
+ * rotation of the normalised quaternion q = (w, x, y, z), real part first.
+ * out[3] receives eta_{R_o} * R_mu.
+ */
+void orc_noise_displacement(const double* q, const double* kappa, double tau, double lr_mu,
+                            const orc_config* cfg, const double* gamma, double* out)
+{
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    double R[3][3] = {
+        {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+        {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+        {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)},
+    };
+    double S2[3] = {exp(2 * kappa[0]), exp(2 * kappa[1]), exp(2 * kappa[2])};
+    double Sigma[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += R[a][j] * S2[j] * R[b][j];
+            Sigma[a][b] = s;
+        }
+    double o = 1.0 / (1.0 + exp(-tau));
+    double gate = 1.0 / (1.0 + exp(cfg->noise_k * (o - cfg->noise_t)));   /* sigma(-k (o - t)) */
+    for (int a = 0; a < 3; ++a) {
+        double sg = Sigma[a][0] * gamma[0] + Sigma[a][1] * gamma[1] + Sigma[a][2] * gamma[2];
+        out[a] = cfg->noise_lr * lr_mu * gate * sg;
+    }
+}
 
 /* Gradient of the L1 regulariser through the activation (Sec. "Implementation
  * Details / AdamW-GS"): the L1 gradient of a positive quantity is +1, so what
@@ -257,8 +341,19 @@ static double reg_grad(int kind, double theta)
  *       u += min(lambda * R'(theta) / N_I' / d, C)   (groups with DAR)
  *       theta <- theta - lr * u
  *     R' is taken at the pre-update theta; d is this step's denominator.
+ *  5. With position noise on, the mean group's elements also move by
+ *     -eta_{R_o} R_mu (orc_noise_displacement), from the pre-update
+ *     quaternion, log-scale and opacity logit of the primitive.
+ *  6. Artificial Implicit Update (AIU, Sec. "Update-step decoupling"): an
+ *     invisible primitive sampled with probability Pro_AIU (an independent
+ *     Bernoulli draw, stream tag 64, compared like the Re-State sample)
+ *     takes an extra update from its moments, which stay unchanged:
+ *       theta <- theta - lr * eta_AIU * (m/b1) / (sqrt(v/b2) + eps)
+ *     with b1, b2 from its current step count (not incremented) and the
+ *     moments after this iteration's Re-State rescale.  A primitive that has
+ *     never been visible (t = 0) has no moments and does not move.
  * The rows may be a subset of a scene: ids[i] (NULL: i) is row i's index in
- * the scene, which keys its Re-State draw.
+ * the scene, which keys its draws.
  */
 void orc_adamw_gs_step_rows(const orc_group* groups, int32_t n_groups, int64_t n,
                             const int64_t* ids, const uint8_t* visible, int32_t* t,
@@ -266,6 +361,8 @@ void orc_adamw_gs_step_rows(const orc_group* groups, int32_t n_groups, int64_t n
 {
     uint64_t thr = cfg->rsr_enable ? orc_rsr_threshold(cfg->rsr_ratio) : 0;
     uint64_t rsr_state = orc_stream_state(cfg->seed, ORC_TAG_RSR, cfg->iteration);
+    uint64_t aiu_thr = cfg->aiu_enable ? orc_rsr_threshold(cfg->aiu_ratio) : 0;
+    uint64_t aiu_state = orc_stream_state(cfg->seed, ORC_TAG_AIU, cfg->iteration);
 
     for (int64_t i = 0; i < n; ++i) {
         if (cfg->rsr_enable) {
@@ -283,14 +380,43 @@ void orc_adamw_gs_step_rows(const orc_group* groups, int32_t n_groups, int64_t n
             }
         }
 
-        if (visible && !visible[i]) continue;
+        if (visible && !visible[i]) {
+            uint64_t id = ids ? (uint64_t)ids[i] : (uint64_t)i;
+            if (!cfg->aiu_enable || t[i] == 0) continue;
+            if ((orc_splitmix_output(aiu_state, id + 1) >> 32) >= aiu_thr) continue;
+            double b1 = 1.0 - pow(cfg->beta1, (double)t[i]);
+            double b2 = 1.0 - pow(cfg->beta2, (double)t[i]);
+            for (int g = 0; g < n_groups; ++g) {
+                const orc_group* G = &groups[g];
+                for (int c = 0; c < G->dim; ++c) {
+                    int64_t e = i * G->dim + c;
+                    double u = (G->m[e] / b1) / (sqrt(G->v[e] / b2) + cfg->eps);
+                    G->param[e] -= G->lr * cfg->aiu_scale * u;
+                }
+            }
+            continue;
+        }
 
         t[i] += 1;
         double b1 = 1.0 - pow(cfg->beta1, (double)t[i]);
         double b2 = 1.0 - pow(cfg->beta2, (double)t[i]);
 
+        /* position noise from the pre-update quaternion, log-scale and
+         * opacity logit of this primitive */
+        double noise[3] = {0.0, 0.0, 0.0};
+        if (cfg->noise_enable) {
+            const orc_group* Gm = &groups[cfg->noise_groups[0]];
+            const orc_group* Gk = &groups[cfg->noise_groups[1]];
+            const orc_group* Gq = &groups[cfg->noise_groups[2]];
+            const orc_group* Go = &groups[cfg->noise_groups[3]];
+            double gamma[3];
+            orc_noise_gamma(cfg->seed, cfg->iteration, ids ? ids[i] : i, gamma);
+            orc_noise_displacement(Gq->param + 4 * i, Gk->param + 3 * i, Go->param[i], Gm->lr, cfg, gamma, noise);
+        }
+
         for (int g = 0; g < n_groups; ++g) {
             const orc_group* G = &groups[g];
+            const int noisy = cfg->noise_enable && g == cfg->noise_groups[0];
             for (int c = 0; c < G->dim; ++c) {
                 int64_t e = i * G->dim + c;
                 double gr = G->grad[e];
@@ -315,6 +441,7 @@ void orc_adamw_gs_step_rows(const orc_group* groups, int32_t n_groups, int64_t n
                     u += r;
                 }
                 G->param[e] = theta - G->lr * u;
+                if (noisy) G->param[e] -= noise[c];
             }
         }
     }
@@ -373,6 +500,57 @@ void orc_reset_state(const orc_group* groups, int32_t n_groups, const int64_t* s
             }
         }
         if (reset_t && t) t[i] = 0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Primitive-set mutation around the step (Sec. "Preliminaries" and the     */
+/* Optimization paragraph of the appendix: densification prunes primitives  */
+/* and generates new ones; "Scaling in RSR": a newly generated primitive's  */
+/* state is that of RSR with alpha1 = alpha2 = 0).                          */
+/* ------------------------------------------------------------------------ */
+
+/* Pruning: the rows with keep[i] != 0, in their order, are copied (theta,
+ * m, v and t) to the front of the destination arrays.  Returns their count.
+ * Gradients are not carried (they belong to one iteration). */
+int64_t orc_prune(const orc_group* src, const orc_group* dst, int32_t n_groups, int64_t n,
+                  const uint8_t* keep, const int32_t* t_src, int32_t* t_dst)
+{
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!keep[i]) continue;
+        for (int g = 0; g < n_groups; ++g) {
+            const orc_group* S = &src[g];
+            const orc_group* D = &dst[g];
+            for (int c = 0; c < S->dim; ++c) {
+                D->param[w * S->dim + c] = S->param[i * S->dim + c];
+                D->m[w * S->dim + c] = S->m[i * S->dim + c];
+                D->v[w * S->dim + c] = S->v[i * S->dim + c];
+            }
+        }
+        t_dst[w] = t_src[i];
+        ++w;
+    }
+    return w;
+}
+
+/* New primitives: row n + j (j < k) takes the attributes of row src_idx[j]
+ * (a clone; the densification policy that then moves or rescales it is the
+ * caller's) and a fresh state, m = v = 0 and t = 0. */
+void orc_append(const orc_group* groups, int32_t n_groups, int64_t n, const int64_t* src_idx, int64_t k,
+                int32_t* t)
+{
+    for (int64_t j = 0; j < k; ++j) {
+        int64_t s = src_idx[j], d = n + j;
+        for (int g = 0; g < n_groups; ++g) {
+            const orc_group* G = &groups[g];
+            for (int c = 0; c < G->dim; ++c) {
+                G->param[d * G->dim + c] = G->param[s * G->dim + c];
+                G->m[d * G->dim + c] = 0.0;
+                G->v[d * G->dim + c] = 0.0;
+            }
+        }
+        t[d] = 0;
     }
 }
 

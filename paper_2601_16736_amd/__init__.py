@@ -69,7 +69,10 @@ class gs_step_config(ctypes.Structure):
                 ("moment_dtype", ctypes.c_int32), ("stochastic_round", ctypes.c_int32),
                 ("rsr_enable", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("rsr_alpha1", ctypes.c_double), ("rsr_alpha2", ctypes.c_double),
-                ("rsr_ratio", ctypes.c_double), ("visible_hint", ctypes.c_float), ("unit", ctypes.c_int32)]
+                ("rsr_ratio", ctypes.c_double), ("visible_hint", ctypes.c_float), ("unit", ctypes.c_int32),
+                ("noise_enable", ctypes.c_int32), ("noise_groups", ctypes.c_int32 * 4), ("noise_lr", ctypes.c_double),
+                ("noise_k", ctypes.c_double), ("noise_t", ctypes.c_double),
+                ("aiu_enable", ctypes.c_int32), ("aiu_ratio", ctypes.c_double), ("aiu_scale", ctypes.c_double)]
 
 
 class gs_scene(ctypes.Structure):
@@ -117,11 +120,19 @@ _lib.gs_spatial_order.restype = _i32
 _lib.gs_spatial_order.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
 _lib.gs_gather_rows.restype = _i32
 _lib.gs_gather_rows.argtypes = [_vp, _vp, _vp, _i64, _i64, _vp]
+_lib.gs_prune_workspace_size.restype = _sz
+_lib.gs_prune_workspace_size.argtypes = [_i64]
+_lib.gs_prune.restype = _i32
+_lib.gs_prune.argtypes = [_vp, _i64, ctypes.POINTER(gs_group), ctypes.POINTER(gs_group), _i32, _i32, _vp, _vp, _vp,
+                          _vp, _sz, _vp]
+_lib.gs_append.restype = _i32
+_lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64, _vp, _vp]
 
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_compact", "adamw_gs_step",
             "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
             "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
-            "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows"]
+            "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
+            "gs_prune", "gs_append"]
 
 
 def _check(status: int) -> None:
@@ -242,6 +253,14 @@ class StepConfig:
     rsr_ratio: float = 0.0
     visible_hint: float = 0.0
     unit: int = 0
+    noise_enable: bool = False
+    noise_groups: tuple = (0, 1, 2, 3)      # mean, log-scale, quaternion, opacity-logit groups
+    noise_lr: float = 0.0                   # eta_{R_o}
+    noise_k: float = 100.0                  # lambda_mu
+    noise_t: float = 0.005                  # lambda_t
+    aiu_enable: bool = False                # Artificial Implicit Update of sampled invisible rows
+    aiu_ratio: float = 0.0                  # Pro_AIU
+    aiu_scale: float = 0.0                  # eta_AIU
 
     def to_c(self) -> gs_step_config:
         c = gs_step_config()
@@ -255,6 +274,12 @@ class StepConfig:
         c.rsr_alpha1, c.rsr_alpha2, c.rsr_ratio = self.rsr_alpha1, self.rsr_alpha2, self.rsr_ratio
         c.visible_hint = float(self.visible_hint)
         c.unit = int(self.unit)
+        c.noise_enable = int(bool(self.noise_enable))
+        for k in range(4):
+            c.noise_groups[k] = int(self.noise_groups[k])
+        c.noise_lr, c.noise_k, c.noise_t = float(self.noise_lr), float(self.noise_k), float(self.noise_t)
+        c.aiu_enable = int(bool(self.aiu_enable))
+        c.aiu_ratio, c.aiu_scale = float(self.aiu_ratio), float(self.aiu_scale)
         return c
 
 
@@ -395,3 +420,28 @@ def apply_spatial_order(tensors, perm, stream=None):
         gs_gather_rows(t.contiguous(), d, perm, stream)
         out.append(d)
     return out
+
+
+# --------------------------------------------------------------------------
+def gs_prune_workspace_size(n: int) -> int:
+    return int(_lib.gs_prune_workspace_size(int(n)))
+
+
+def gs_prune(keep, src: Sequence[Group], dst: Sequence[Group], moment_dtype: int, t_src, t_dst, kept_count,
+             workspace, stream=None) -> None:
+    """Order-preserving compaction of theta, m, v and t by ``keep`` into dst."""
+    if len(src) != len(dst):
+        raise ValueError("src and dst need the same groups")
+    a, b = _groups_c(src), _groups_c(dst)
+    n = int(keep.shape[0])
+    ws_bytes = int(workspace.numel() * workspace.element_size()) if workspace is not None else 0
+    _check(_lib.gs_prune(_ptr(keep), n, a, b, len(src), int(moment_dtype), _ptr(t_src), _ptr(t_dst),
+                         _ptr(kept_count), _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def gs_append(groups: Sequence[Group], moment_dtype: int, n: int, src_idx, step_count, stream=None) -> None:
+    """Rows n .. n+k-1 become clones of rows src_idx with zero state."""
+    arr = _groups_c(groups)
+    k = int(src_idx.shape[0]) if src_idx is not None else 0
+    _check(_lib.gs_append(arr, len(groups), int(moment_dtype), int(n), _ptr(src_idx), k, _ptr(step_count),
+                          _stream(stream)))

@@ -112,6 +112,14 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
     return GS_OK;
 }
 
+// Bernoulli(p) sampling threshold on the top 32 bits of a draw.
+static uint64_t sample_threshold(double p)
+{
+    if (p >= 1.0) return (uint64_t)1 << 32;
+    if (p > 0.0) return (uint64_t)std::floor(p * 4294967296.0);
+    return 0;
+}
+
 gs_status build_hyper(const gs_step_config* cfg, bool need_reg_norm, KHyper* h)
 {
     if (cfg == nullptr) return fail(GS_EINVAL, "cfg is NULL");
@@ -144,15 +152,40 @@ gs_status build_hyper(const gs_step_config* cfg, bool need_reg_norm, KHyper* h)
     h->c1_rsr = (float)(cfg->beta1 * cfg->rsr_alpha1);
     h->c2_rsr = (float)(cfg->beta2 * cfg->rsr_alpha2);
     h->sr = (cfg->moment_dtype == GS_MOMENT_BF16 && cfg->stochastic_round) ? 1 : 0;
-    uint64_t thr = 0;
-    if (cfg->rsr_enable) {
-        if (cfg->rsr_ratio >= 1.0) thr = (uint64_t)1 << 32;
-        else if (cfg->rsr_ratio > 0.0) thr = (uint64_t)std::floor(cfg->rsr_ratio * 4294967296.0);
-    }
-    h->rsr_thr = thr;
+    h->rsr_thr = cfg->rsr_enable ? sample_threshold(cfg->rsr_ratio) : 0;
+    if (cfg->aiu_enable && (!(cfg->aiu_ratio >= 0.0 && cfg->aiu_ratio <= 1.0) || !(cfg->aiu_scale >= 0.0) ||
+                            !finite_d(cfg->aiu_scale)))
+        return fail(GS_EINVAL, "aiu_ratio must be in [0, 1] and aiu_scale finite and >= 0");
+    h->aiu_thr = cfg->aiu_enable ? sample_threshold(cfg->aiu_ratio) : 0;
+    h->aiu_scale = cfg->aiu_enable ? cfg->aiu_scale : 0.0;
     h->seed = cfg->seed;
     h->reg_norm = cfg->reg_norm;
     h->iteration = cfg->iteration;
+    h->noise = cfg->noise_enable ? 1 : 0;
+    for (int k = 0; k < 4; ++k) h->noise_g[k] = cfg->noise_enable ? cfg->noise_groups[k] : 0;
+    h->noise_lr = cfg->noise_enable ? cfg->noise_lr : 0.0;
+    h->noise_k = (float)cfg->noise_k;
+    h->noise_t = (float)cfg->noise_t;
+    if (cfg->noise_enable && (!(cfg->noise_lr >= 0.0) || !finite_d(cfg->noise_lr) || !finite_d(cfg->noise_k) ||
+                              !finite_d(cfg->noise_t)))
+        return fail(GS_EINVAL, "noise_lr must be finite and >= 0; noise_k, noise_t finite");
+    return GS_OK;
+}
+
+// Position noise reads the quaternion, log-scale and opacity groups of the
+// scene: their indices and dims must fit.
+gs_status check_noise_groups(const gs_step_config* cfg, const gs_group* groups, int32_t n_groups, const char* prefix)
+{
+    if (!cfg->noise_enable) return GS_OK;
+    static const int dims[4] = {3, 3, 4, 1};
+    for (int k = 0; k < 4; ++k) {
+        const int g = cfg->noise_groups[k];
+        if (g < 0 || g >= n_groups) return fail(GS_EINVAL, "%snoise_groups[%d] = %d out of range", prefix, k, g);
+        if (groups[g].dim != dims[k])
+            return fail(GS_EINVAL, "%snoise_groups[%d] = %d has dim %d, expected %d", prefix, k, g, groups[g].dim, dims[k]);
+        for (int j = 0; j < k; ++j)
+            if (cfg->noise_groups[j] == g) return fail(GS_EINVAL, "%snoise_groups must be distinct", prefix);
+    }
     return GS_OK;
 }
 
@@ -289,21 +322,23 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     memset(&s, 0, sizeof s);
     st = build_groups(groups, n_groups, n, cfg->moment_dtype, cfg, &s, "");
     if (st != GS_OK) return st;
+    st = check_noise_groups(cfg, groups, n_groups, "");
+    if (st != GS_OK) return st;
     int32_t dims[GS_MAX_GROUPS];
     for (int g = 0; g < n_groups; ++g) dims[g] = groups[g].dim;
     int sched = 0, unit = 0;
     st = resolve_schedule(cfg->schedule, cfg->unit, cfg->visible_hint, n, n_groups, dims, cfg->moment_dtype, visible,
                           vis_idx, vis_count, &sched, &unit, "");
     if (st != GS_OK) return st;
-    if (n > 0 && cfg->rsr_enable && h.rsr_thr > 0 && sched != kSchedDense && visible == nullptr)
-        return fail(GS_EINVAL, "RSR with a sparse schedule needs the visibility mask (to rescale invisible rows)");
+    if (n > 0 && (h.rsr_thr > 0 || h.aiu_thr > 0) && sched != kSchedDense && visible == nullptr)
+        return fail(GS_EINVAL, "RSR or AIU with a sparse schedule needs the visibility mask (to find invisible rows)");
     s.sched = sched;
     s.unit = unit;
     s.mask = visible;
     s.idx = vis_idx;
     s.count = vis_count;
     s.t = step_count;
-    const hipError_t e = launch_step(s, h, cfg->rsr_enable != 0 && h.rsr_thr > 0, stream);
+    const hipError_t e = launch_step(s, h, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step launch");
 }
 

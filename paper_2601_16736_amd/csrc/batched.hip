@@ -4,7 +4,8 @@
 // launch of a persistent grid (sized from the kernel's occupancy) whose waves
 // pull work units from a global atomic counter: first every scene's step
 // units (index-list slices or mask windows, per the scene's schedule), then,
-// on Re-State iterations, every scene's windows of invisible sampled rows.
+// on Re-State or AIU iterations, every scene's windows of invisible sampled
+// rows.
 // The last wave to finish resets the counters, so consecutive launches need
 // no clearing.  The launch is a HIP graph with one kernel node whose
 // arguments (the step's scalars) are replaced before each replay.
@@ -28,12 +29,12 @@ namespace {
 
 constexpr int kMaxScenes = kWave;     // one lane per scene when counting units
 constexpr int kBatchCap = 512;
-constexpr int kRsrWindow = 512;
+constexpr int kInvWindow = 512;
 
 struct KBatch {
     const KScene* scenes;
     int32_t n_scenes;
-    int32_t rsr;          // Re-State units for invisible sampled rows this step
+    int32_t inv;          // units of invisible sampled rows (Re-State or AIU) this step
     int32_t* queue;       // [0] next unit, [1] waves finished
     int32_t total_waves;
     int32_t pad;
@@ -48,12 +49,12 @@ __device__ __forceinline__ int scene_step_units(const KScene& S)
     return (int)((S.n + S.unit - 1) / S.unit);
 }
 
-__device__ __forceinline__ int scene_rsr_units(const KScene& S, int rsr)
+__device__ __forceinline__ int scene_inv_units(const KScene& S, int inv)
 {
-    return (rsr && S.sched != kSchedDense && S.mask != nullptr) ? (int)((S.n + kRsrWindow - 1) / kRsrWindow) : 0;
+    return (inv && S.sched != kSchedDense && S.mask != nullptr) ? (int)((S.n + kInvWindow - 1) / kInvWindow) : 0;
 }
 
-template <bool BF16>
+template <bool BF16, bool NOISE>
 __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, float* s_rb1,
                                           float* s_rsb2, int lane)
 {
@@ -81,25 +82,28 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         wave_sync();
         stage_step_rows(nrows, s_row, s_rb1, s_rsb2, S.t, H, d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
-        step_all_groups<BF16>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
+        step_all_groups<BF16, NOISE>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
     }
     wave_sync();   // the next unit reuses this wave's LDS rows
 }
 
 template <bool BF16>
-__device__ __forceinline__ void rsr_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, int lane)
+__device__ __forceinline__ void invisible_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row,
+                                               float* s_rb1, float* s_rsb2, int lane)
 {
     const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
-    const uint64_t s2 = d_stream(seed, kTagRsr, H.iteration);
-    const int nrows = build_rows_sampled<kRsrWindow>(S.mask, S.n, local * kRsrWindow, s2, H.rsr_thr, s_row, lane);
+    const int nrows = build_rows_invisible<kInvWindow>(S.mask, S.n, local * kInvWindow, S.t, H,
+                                                       d_stream(seed, kTagRsr, H.iteration),
+                                                       d_stream(seed, kTagAiu, H.iteration), s_row, s_rb1, s_rsb2,
+                                                       lane);
     if (nrows > 0) {
         wave_sync();
-        rsr_all_groups<BF16>(S, H, seed, nrows, s_row, lane);
+        invisible_all_groups<BF16>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
     }
     wave_sync();
 }
 
-template <bool BF16>
+template <bool BF16, bool NOISE>
 __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
 {
     __shared__ int s_row[kWavesPerBlock][kBatchCap];
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
     if (lane < B.n_scenes) {
         const KScene& S = B.scenes[lane];
         su = scene_step_units(S);
-        ru = scene_rsr_units(S, B.rsr);
+        ru = scene_inv_units(S, B.inv);
     }
     const int mine = su + ru;
     int incl = mine;
@@ -135,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
         const int steps_s = __builtin_amdgcn_readfirstlane(__shfl(su, s));
         const KScene& S = B.scenes[s];
         const int local = u - start;
-        if (local < steps_s) step_unit<BF16>(S, H, local, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
-        else rsr_unit<BF16>(S, H, local - steps_s, s_row[wave], lane);
+        if (local < steps_s) step_unit<BF16, NOISE>(S, H, local, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+        else invisible_unit<BF16>(S, H, local - steps_s, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
     }
 
     // every wave checks out; the last one resets the counters for the next launch
@@ -163,10 +167,10 @@ struct gs_batch {
     std::vector<int32_t> sched;
     KScene* d_scenes = nullptr;
     int32_t* d_queue = nullptr;
-    int grid = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t node = nullptr;
+    int grid[2] = {0, 0};                // per kernel variant: [0] plain, [1] position noise
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphNode_t node[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
     KBatch kb{};
     KHyper kh{};
@@ -174,17 +178,22 @@ struct gs_batch {
 
 namespace {
 
-void* kernel_for(int moment_dtype)
+void* kernel_for(int moment_dtype, int noise)
 {
-    return moment_dtype == GS_MOMENT_BF16 ? reinterpret_cast<void*>(&batched_kernel<true>)
-                                          : reinterpret_cast<void*>(&batched_kernel<false>);
+    if (moment_dtype == GS_MOMENT_BF16)
+        return noise ? reinterpret_cast<void*>(&batched_kernel<true, true>)
+                     : reinterpret_cast<void*>(&batched_kernel<true, false>);
+    return noise ? reinterpret_cast<void*>(&batched_kernel<false, true>)
+                 : reinterpret_cast<void*>(&batched_kernel<false, false>);
 }
 
 void free_batch(gs_batch* b)
 {
     if (b == nullptr) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int v = 0; v < 2; ++v) {
+        if (b->exec[v]) (void)hipGraphExecDestroy(b->exec[v]);
+        if (b->graph[v]) (void)hipGraphDestroy(b->graph[v]);
+    }
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->d_scenes) (void)hipFree(b->d_scenes);
     if (b->d_queue) (void)hipFree(b->d_queue);
@@ -252,13 +261,17 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
         K.t = sc.step_count;
         b->sched[(size_t)s] = sched;
     }
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel_for(moment_dtype)),
-                                                     kBlock, 0) != hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail_batch(b, GS_EHIP, "gs_batch_create: device query failed");
-    b->grid = std::max(1, cus * std::max(1, per_cu));
+    for (int v = 0; v < 2; ++v) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(kernel_for(moment_dtype, v)), kBlock, 0) != hipSuccess)
+            return fail_batch(b, GS_EHIP, "gs_batch_create: occupancy query failed");
+        b->grid[v] = std::max(1, cus * std::max(1, per_cu));
+    }
     if (hipMalloc(&b->d_scenes, sizeof(KScene) * (size_t)n_scenes) != hipSuccess ||
         hipMalloc(&b->d_queue, 2 * sizeof(int32_t)) != hipSuccess)
         return fail_batch(b, GS_ENOMEM, "gs_batch_create: hipMalloc failed");
@@ -270,7 +283,6 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
     b->kb.scenes = b->d_scenes;
     b->kb.n_scenes = n_scenes;
     b->kb.queue = b->d_queue;
-    b->kb.total_waves = b->grid * kWavesPerBlock;
     *out = b;
     return GS_OK;
 }
@@ -285,26 +297,47 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     KHyper h;
     gs_status st = build_hyper(cfg, b->any_adaptive, &h);
     if (st != GS_OK) return st;
+    if (cfg->noise_enable) {
+        static const int dims[4] = {3, 3, 4, 1};
+        for (const KScene& K : b->h_scenes)
+            for (int k = 0; k < 4; ++k) {
+                const int g = cfg->noise_groups[k];
+                bool dup = false;
+                for (int j = 0; j < k; ++j) dup = dup || cfg->noise_groups[j] == g;
+                if (g < 0 || g >= K.n_groups || K.g[g].dim != dims[k] || dup)
+                    return set_error(GS_EINVAL, "adamw_gs_step_batched: noise_groups do not fit every scene");
+            }
+    }
+    if (h.rsr_thr > 0 || h.aiu_thr > 0)
+        for (const KScene& K : b->h_scenes)
+            if (K.n > 0 && K.sched != kSchedDense && K.mask == nullptr)
+                return set_error(GS_EINVAL, "adamw_gs_step_batched: RSR or AIU needs every sparse scene's "
+                                            "visibility mask (to find invisible rows)");
+    // Each variant has its own graph: a kernel node keeps the function it
+    // was created with, and the wave count that resets the queue is the
+    // variant's own grid.
+    const int v = h.noise ? 1 : 0;
     b->kh = h;
-    b->kb.rsr = (cfg->rsr_enable && h.rsr_thr > 0) ? 1 : 0;
+    b->kb.inv = (h.rsr_thr > 0 || h.aiu_thr > 0) ? 1 : 0;
+    b->kb.total_waves = b->grid[v] * kWavesPerBlock;
     void* args[] = {&b->kb, &b->kh};
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
-    p.func = kernel_for(b->moment_dtype);
-    p.gridDim = dim3((unsigned)b->grid);
+    p.func = kernel_for(b->moment_dtype, v);
+    p.gridDim = dim3((unsigned)b->grid[v]);
     p.blockDim = dim3(kBlock);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
     p.extra = nullptr;
     hipError_t e = hipSuccess;
-    if (b->exec == nullptr) {
-        e = hipGraphCreate(&b->graph, 0);
-        if (e == hipSuccess) e = hipGraphAddKernelNode(&b->node, b->graph, nullptr, 0, &p);
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (b->exec[v] == nullptr) {
+        e = hipGraphCreate(&b->graph[v], 0);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&b->node[v], b->graph[v], nullptr, 0, &p);
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[v], b->graph[v], nullptr, nullptr, 0);
     } else {
-        e = hipGraphExecKernelNodeSetParams(b->exec, b->node, &p);
+        e = hipGraphExecKernelNodeSetParams(b->exec[v], b->node[v], &p);
     }
-    if (e == hipSuccess) e = hipGraphLaunch(b->exec, stream);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec[v], stream);
     if (e == hipSuccess) e = hipEventRecord(b->done, stream);
     if (e != hipSuccess) return set_error(GS_EHIP, hipGetErrorString(e));
     return GS_OK;

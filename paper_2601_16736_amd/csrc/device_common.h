@@ -202,13 +202,61 @@ __device__ __forceinline__ float reg_term(int kind, int mode, float scale, float
     return fminf(scale * R, clip);
 }
 
+// Component c of the position-noise displacement eta_{R_o} R_mu of primitive
+// i (definition in gsopt.h): Sigma gamma from the pre-update quaternion and
+// log-scale, gated by the pre-update opacity.  `scale` = eta_{R_o} eta_mu.
+__device__ __forceinline__ float noise_component(const float* qp, const float* kp, const float* tp, int64_t i,
+                                                 int c, uint64_t s2, float scale, float k, float t0)
+{
+    // gamma ~ N(0, I3): Box-Muller on 24-bit uniforms of two draws
+    const uint64_t d1 = d_splitmix(s2, 2 * (uint64_t)i + 1);
+    const uint64_t d2 = d_splitmix(s2, 2 * (uint64_t)i + 2);
+    const float u1 = (float)((uint32_t)(d1 >> 40) + 1u) * 0x1p-24f;
+    const float a1 = (float)((uint32_t)(d1 >> 8) & 0xFFFFFFu) * 0x1p-24f;
+    const float u2 = (float)((uint32_t)(d2 >> 40) + 1u) * 0x1p-24f;
+    const float a2 = (float)((uint32_t)(d2 >> 8) & 0xFFFFFFu) * 0x1p-24f;
+    const float r1 = __fsqrt_rn(-2.0f * logf(u1));
+    const float r2 = __fsqrt_rn(-2.0f * logf(u2));
+    float sn1, cs1, sn2, cs2;
+    sincospif(2.0f * a1, &sn1, &cs1);
+    sincospif(2.0f * a2, &sn2, &cs2);
+    const float g0 = r1 * cs1, g1 = r1 * sn1, g2 = r2 * cs2;
+    // rotation of the normalised quaternion (w, x, y, z)
+    float w = qp[4 * i], x = qp[4 * i + 1], y = qp[4 * i + 2], z = qp[4 * i + 3];
+    const float inv = 1.0f / __fsqrt_rn(w * w + x * x + y * y + z * z);
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    const float R00 = 1.0f - 2.0f * (y * y + z * z), R01 = 2.0f * (x * y - w * z), R02 = 2.0f * (x * z + w * y);
+    const float R10 = 2.0f * (x * y + w * z), R11 = 1.0f - 2.0f * (x * x + z * z), R12 = 2.0f * (y * z - w * x);
+    const float R20 = 2.0f * (x * z - w * y), R21 = 2.0f * (y * z + w * x), R22 = 1.0f - 2.0f * (x * x + y * y);
+    // Sigma gamma = R diag(exp(2 kappa)) R^T gamma
+    const float e0 = (R00 * g0 + R10 * g1 + R20 * g2) * expf(2.0f * kp[3 * i]);
+    const float e1 = (R01 * g0 + R11 * g1 + R21 * g2) * expf(2.0f * kp[3 * i + 1]);
+    const float e2 = (R02 * g0 + R12 * g1 + R22 * g2) * expf(2.0f * kp[3 * i + 2]);
+    const float sg = c == 0 ? R00 * e0 + R01 * e1 + R02 * e2
+                   : c == 1 ? R10 * e0 + R11 * e1 + R12 * e2
+                            : R20 * e0 + R21 * e1 + R22 * e2;
+    const float o = 1.0f / (1.0f + expf(-tp[i]));
+    const float gate = 1.0f / (1.0f + expf(k * (o - t0)));            // sigma(-k (o - t))
+    return scale * gate * sg;
+}
+
+struct NoiseArgs {
+    const float* q;      // quaternion group's attributes
+    const float* kappa;  // log-scale group's attributes
+    const float* tau;    // opacity-logit group's attributes
+    uint64_t s2;         // stream (seed, tag 48, iteration)
+    float scale;         // eta_{R_o} * eta_mu
+};
+
 // One group's read-modify-write pass over the wave's staged rows.  Each
 // lane takes U (row, chunk) items per trip and issues all their loads before
-// any store, so a wave keeps U x 4 vector loads in flight.
-template <bool BF16, int V, int U>
+// any store, so a wave keeps U x 4 vector loads in flight.  NOISE (mean
+// group only, V = 1) subtracts the position-noise displacement after the
+// Adam update.
+template <bool BF16, int V, int U, bool NOISE = false>
 __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int nrows,
                                            const int* s_row, const float* s_rb1, const float* s_rsb2,
-                                           int lane, float dar_scale, uint64_t sr_s2)
+                                           int lane, float dar_scale, uint64_t sr_s2, const NoiseArgs* nz = nullptr)
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
@@ -263,6 +311,11 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
 #endif
                 if (dar) uu += reg_term(G.dar_kind, G.reg_mode, dar_scale, G.dar_clip, th[u][q], d);
                 th[u][q] = th[u][q] - G.lr * uu;
+                if constexpr (NOISE) {
+                    const int64_t prim = e[u] / 3;          // the mean group has dim 3 (and V = 1)
+                    th[u][q] -= noise_component(nz->q, nz->kappa, nz->tau, prim, (int)(e[u] - prim * 3), nz->s2,
+                                                nz->scale, H.noise_k, H.noise_t);
+                }
                 m[u][q] = mm;
                 v[u][q] = vv;
             }
@@ -272,10 +325,15 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
     }
 }
 
-// One group's Re-State rescale of the wave's staged rows: m <- a1 m, v <- a2 v.
+// One group's pass over the wave's staged invisible rows.  A row tagged in
+// its sign bit is in this iteration's Re-State sample: m <- a1 m, v <- a2 v,
+// stored.  A row with rb1 > 0 is in the AIU sample: theta moves by
+// -lr eta_AIU (m rb1)/(sqrt(v) rsb2 + eps) from the (rescaled) moments,
+// which are not stored again unless the row was rescaled.
 template <bool BF16, int V>
-__device__ __forceinline__ void rsr_group(const KGroup& G, const KHyper& H, int nrows, const int* s_row,
-                                          int lane, uint64_t sr_s2)
+__device__ __forceinline__ void invisible_group(const KGroup& G, const KHyper& H, int nrows, const int* s_row,
+                                                const float* s_rb1, const float* s_rsb2, int lane, uint64_t sr_s2,
+                                                float lr_aiu)
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
@@ -285,16 +343,32 @@ __device__ __forceinline__ void rsr_group(const KGroup& G, const KHyper& H, int 
     const int dr = kWave / cpr;
     const int dc = kWave - dr * cpr;
     for (int k = lane; k < items; k += kWave) {
-        const int64_t e = (int64_t)s_row[r] * dim + c * V;
-        float m[V], v[V];
+        const int raw = s_row[r];
+        const float rb1 = s_rb1[r];
+        const float rsb2 = s_rsb2[r];
+        const bool rsr = raw < 0;
+        const bool aiu = rb1 > 0.0f;
+        const int64_t e = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
+        float m[V], v[V], th[V];
         load_moment<BF16, V>(G.m, e, m);
         load_moment<BF16, V>(G.v, e, v);
+        if (aiu) load_f<V>(G.param + e, th);
+        if (rsr) {
 #pragma unroll
-        for (int q = 0; q < V; ++q) {
-            m[q] = H.rsr_a1 * m[q];
-            v[q] = H.rsr_a2 * v[q];
+            for (int q = 0; q < V; ++q) {
+                m[q] = H.rsr_a1 * m[q];
+                v[q] = H.rsr_a2 * v[q];
+            }
+            store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
         }
-        store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
+        if (aiu) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const float d = __fsqrt_rn(v[q]) * rsb2 + H.eps;
+                th[q] = th[q] - lr_aiu * ((m[q] * rb1) / d);
+            }
+            store_f<V>(G.param + e, th);
+        }
         r += dr;
         c += dc;
         if (c >= cpr) { c -= cpr; ++r; }
@@ -332,18 +406,38 @@ __device__ __forceinline__ bool rsr_sampled(uint64_t s2, uint64_t thr, int64_t i
     return (d_splitmix(s2, (uint64_t)i + 1) >> 32) < thr;
 }
 
-// Sampled rows of a window that the step itself does not visit (mask == 0).
+// Invisible rows of a window (mask == 0) in this iteration's Re-State sample
+// or, with t > 0, in its AIU sample, in ascending order.  Re-State rows get
+// the sign bit; AIU rows get their bias factors from the unchanged t, other
+// rows rb1 = 0.
 template <int UNIT>
-__device__ __forceinline__ int build_rows_sampled(const uint8_t* mask, int64_t n, int64_t w0, uint64_t s2,
-                                                  uint64_t thr, int* s_row, int lane)
+__device__ __forceinline__ int build_rows_invisible(const uint8_t* mask, int64_t n, int64_t w0, const int32_t* t,
+                                                    const KHyper& H, uint64_t rsr_s2, uint64_t aiu_s2, int* s_row,
+                                                    float* s_rb1, float* s_rsb2, int lane)
 {
     int nrows = 0;
 #pragma unroll
     for (int b = 0; b < UNIT / kWave; ++b) {
         const int64_t i = w0 + b * kWave + lane;
-        const bool pick = i < n && mask[i] == 0 && rsr_sampled(s2, thr, i);
+        const bool inv = i < n && mask[i] == 0;
+        const bool rsr = inv && H.rsr_thr != 0 && rsr_sampled(rsr_s2, H.rsr_thr, i);
+        int ti = 0;
+        if (inv && H.aiu_thr != 0 && rsr_sampled(aiu_s2, H.aiu_thr, i)) ti = t[i];
+        const bool aiu = ti > 0;
+        const bool pick = rsr || aiu;
         const uint64_t bal = __ballot(pick);
-        if (pick) s_row[nrows + lanes_below(bal)] = (int)i;
+        if (pick) {
+            const int j = nrows + lanes_below(bal);
+            s_row[j] = rsr ? (int)((uint32_t)i | 0x80000000u) : (int)i;
+            float rb1 = 0.0f, rsb2 = 0.0f;
+            if (aiu) {
+                const float ft = (float)ti;
+                rb1 = 1.0f / -expm1f(ft * H.logb1);
+                rsb2 = 1.0f / __fsqrt_rn(-expm1f(ft * H.logb2));
+            }
+            s_rb1[j] = rb1;
+            s_rsb2[j] = rsb2;
+        }
         nrows += __popcll(bal);
     }
     return nrows;
@@ -398,13 +492,35 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
 #define GS_STEP_UNROLL 2
 #endif
 
-template <bool BF16>
+template <bool BF16, bool NOISE>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
                                                 const int* s_row, const float* s_rb1, const float* s_rsb2,
                                                 int lane)
 {
     constexpr int U = GS_STEP_UNROLL;
+    // With position noise the mean group goes first, so the quaternion,
+    // log-scale and opacity rows it reads are still the pre-update ones.
+    // Groups are indexed directly (no switch over constant indices): the
+    // by-value scene then stays in the kernel arguments instead of being
+    // copied to private memory.  The noise code is compiled only into the
+    // NOISE kernels, so the plain step keeps its register budget.
+    const int first = NOISE ? H.noise_g[0] : -1;
+    if constexpr (NOISE) {
+        const KGroup& G = S.g[first];
+        NoiseArgs nz;
+        nz.q = S.g[H.noise_g[2]].param;
+        nz.kappa = S.g[H.noise_g[1]].param;
+        nz.tau = S.g[H.noise_g[3]].param;
+        nz.s2 = d_stream(seed, kTagNoise, H.iteration);
+        nz.scale = (float)(H.noise_lr * (double)G.lr);
+        const float dar_scale = (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
+                                    ? (float)(G.dar_lambda / H.reg_norm)
+                                    : (float)G.dar_lambda;
+        const uint64_t s2 = BF16 ? d_stream(seed, kTagSrStep + (uint64_t)first, H.iteration) : 0;
+        step_group<BF16, 1, U * 2, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, &nz);
+    }
     for (int gi = 0; gi < S.n_groups; ++gi) {
+        if (gi == first) continue;
         const KGroup& G = S.g[gi];
         // lambda / N_I' rounded once from double, exactly as a host would form it
         const float dar_scale = (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
@@ -418,15 +534,17 @@ __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H
 }
 
 template <bool BF16>
-__device__ __forceinline__ void rsr_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
-                                               const int* s_row, int lane)
+__device__ __forceinline__ void invisible_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
+                                                     const int* s_row, const float* s_rb1, const float* s_rsb2,
+                                                     int lane)
 {
     for (int gi = 0; gi < S.n_groups; ++gi) {
         const KGroup& G = S.g[gi];
         const uint64_t s2 = BF16 ? d_stream(seed, kTagSrRsr + (uint64_t)gi, H.iteration) : 0;
-        if (G.vec == 4) rsr_group<BF16, 4>(G, H, nrows, s_row, lane, s2);
-        else if (G.vec == 2) rsr_group<BF16, 2>(G, H, nrows, s_row, lane, s2);
-        else rsr_group<BF16, 1>(G, H, nrows, s_row, lane, s2);
+        const float lr_aiu = (float)((double)G.lr * H.aiu_scale);
+        if (G.vec == 4) invisible_group<BF16, 4>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2, lr_aiu);
+        else if (G.vec == 2) invisible_group<BF16, 2>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2, lr_aiu);
+        else invisible_group<BF16, 1>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, s2, lr_aiu);
     }
 }
 

@@ -14,7 +14,7 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kCap = 512;            // max rows a wave stages per unit
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 
-enum : uint64_t { kTagRsr = 1, kTagSrStep = 16, kTagSrRsr = 32 };
+enum : uint64_t { kTagRsr = 1, kTagSrStep = 16, kTagSrRsr = 32 };   // kTagSrRsr: rounding in the invisible pass
 enum : int { kSchedCompacted = 1, kSchedMasked = 2, kSchedDense = 3 };
 
 // One attribute group as the kernels see it.
@@ -46,7 +46,17 @@ struct KHyper {
     uint64_t seed;                    // draws of scene s use seed + s (see KScene::seed_offset)
     double reg_norm;                  // N_I'
     int64_t iteration;
+    // position noise on the mean group
+    int32_t noise;                    // 1 = on
+    int32_t noise_g[4];               // groups: mean, log-scale, quaternion, opacity logit
+    double noise_lr;                  // eta_{R_o} (multiplied by the mean group's lr on the device, in double)
+    float noise_k, noise_t;           // lambda_mu, lambda_t
+    // Artificial Implicit Update of sampled invisible rows
+    uint64_t aiu_thr;                 // sampled iff draw >> 32 < aiu_thr; 0 = off
+    double aiu_scale;                 // eta_AIU (multiplied by each group's lr on the device, in double)
 };
+
+enum : uint64_t { kTagNoise = 48, kTagAiu = 64 };
 
 // One scene: its groups, visibility inputs and schedule.
 struct KScene {
@@ -77,8 +87,9 @@ uint64_t splitmix_output(uint64_t s, uint64_t k);
 hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
                              uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream);
-hipError_t launch_step(const KScene& s, const KHyper& h, bool rsr, hipStream_t stream);
-hipError_t launch_rsr(const KScene& s, const KHyper& h, hipStream_t stream);
+// The invisible-row pass (Re-State / AIU samples) runs first when either is on.
+hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream);
+hipError_t launch_invisible(const KScene& s, const KHyper& h, hipStream_t stream);
 size_t step_kernel_units(const KScene& s);
 
 // batched

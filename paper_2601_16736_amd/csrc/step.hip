@@ -9,7 +9,8 @@ namespace gs {
 //   masked:    visible primitives of the window [unit*UNIT, unit*UNIT + UNIT)
 //   dense:     every primitive of that window (V = 1)
 // The grid covers the largest possible unit count; waves past the end exit.
-template <bool BF16, int SCHED, int UNIT>
+// NOISE adds the position-noise displacement to the mean group.
+template <bool BF16, int SCHED, int UNIT, bool NOISE>
 __global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
 {
     __shared__ int s_row[kWavesPerBlock][UNIT];
@@ -35,59 +36,63 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
     stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H, d_stream(seed, kTagRsr, H.iteration),
                     lane);
     wave_sync();
-    step_all_groups<BF16>(S, H, seed, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+    step_all_groups<BF16, NOISE>(S, H, seed, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
 }
 
-// Re-State pass over the primitives the step does not visit (mask == 0):
-// each wave takes a window of 512, stages the sampled invisible rows and
-// rescales their moments in every group.  Sampled visible rows are rescaled
-// inside the step kernel, in registers, before their moment update.
-constexpr int kRsrUnit = 512;
+// Pass over the primitives the step does not visit (mask == 0): each wave
+// takes a window of 512, stages the invisible rows in this iteration's
+// Re-State or AIU sample and applies both in every group.  Sampled visible
+// rows are rescaled inside the step kernel, in registers, before their
+// moment update.
+constexpr int kInvUnit = 512;
 
 template <bool BF16>
-__global__ __launch_bounds__(kBlock) void rsr_kernel(KScene S, KHyper H)
+__global__ __launch_bounds__(kBlock) void invisible_kernel(KScene S, KHyper H)
 {
-    __shared__ int s_row[kWavesPerBlock][kRsrUnit];
+    __shared__ int s_row[kWavesPerBlock][kInvUnit];
+    __shared__ float s_rb1[kWavesPerBlock][kInvUnit];
+    __shared__ float s_rsb2[kWavesPerBlock][kInvUnit];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRsrUnit;
+    const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kInvUnit;
     if (w0 >= S.n) return;
     const uint64_t seed = H.seed + (uint64_t)S.seed_offset;
-    const uint64_t s2 = d_stream(seed, kTagRsr, H.iteration);
-    const int nrows = build_rows_sampled<kRsrUnit>(S.mask, S.n, w0, s2, H.rsr_thr, s_row[wave], lane);
+    const int nrows = build_rows_invisible<kInvUnit>(S.mask, S.n, w0, S.t, H, d_stream(seed, kTagRsr, H.iteration),
+                                                     d_stream(seed, kTagAiu, H.iteration), s_row[wave],
+                                                     s_rb1[wave], s_rsb2[wave], lane);
     if (nrows == 0) return;
     wave_sync();
-    rsr_all_groups<BF16>(S, H, seed, nrows, s_row[wave], lane);
+    invisible_all_groups<BF16>(S, H, seed, nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
 }
 
 namespace {
 
 using StepFn = void (*)(KScene, KHyper);
 
-template <bool BF16>
+template <bool BF16, bool NOISE>
 StepFn pick(int sched, int unit)
 {
     if (sched == kSchedCompacted) {
         switch (unit) {
-        case 64: return step_kernel<BF16, kSchedCompacted, 64>;
-        case 128: return step_kernel<BF16, kSchedCompacted, 128>;
-        case 256: return step_kernel<BF16, kSchedCompacted, 256>;
-        case 512: return step_kernel<BF16, kSchedCompacted, 512>;
+        case 64: return step_kernel<BF16, kSchedCompacted, 64, NOISE>;
+        case 128: return step_kernel<BF16, kSchedCompacted, 128, NOISE>;
+        case 256: return step_kernel<BF16, kSchedCompacted, 256, NOISE>;
+        case 512: return step_kernel<BF16, kSchedCompacted, 512, NOISE>;
         default: return nullptr;
         }
     }
     if (sched == kSchedMasked) {
         switch (unit) {
-        case 128: return step_kernel<BF16, kSchedMasked, 128>;
-        case 256: return step_kernel<BF16, kSchedMasked, 256>;
-        case 512: return step_kernel<BF16, kSchedMasked, 512>;
+        case 128: return step_kernel<BF16, kSchedMasked, 128, NOISE>;
+        case 256: return step_kernel<BF16, kSchedMasked, 256, NOISE>;
+        case 512: return step_kernel<BF16, kSchedMasked, 512, NOISE>;
         default: return nullptr;
         }
     }
     if (sched == kSchedDense) {
         switch (unit) {
-        case 256: return step_kernel<BF16, kSchedDense, 256>;
-        case 512: return step_kernel<BF16, kSchedDense, 512>;
+        case 256: return step_kernel<BF16, kSchedDense, 256, NOISE>;
+        case 512: return step_kernel<BF16, kSchedDense, 512, NOISE>;
         default: return nullptr;
         }
     }
@@ -101,14 +106,15 @@ size_t step_kernel_units(const KScene& s)
     return (size_t)((s.n + s.unit - 1) / s.unit);
 }
 
-hipError_t launch_step(const KScene& s, const KHyper& h, bool rsr, hipStream_t stream)
+hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream)
 {
     if (s.n == 0) return hipSuccess;
-    if (rsr && s.sched != kSchedDense) {
-        const hipError_t e = launch_rsr(s, h, stream);
+    if (s.sched != kSchedDense) {
+        const hipError_t e = launch_invisible(s, h, stream);
         if (e != hipSuccess) return e;
     }
-    StepFn fn = s.bf16 ? pick<true>(s.sched, s.unit) : pick<false>(s.sched, s.unit);
+    StepFn fn = s.bf16 ? (h.noise ? pick<true, true>(s.sched, s.unit) : pick<true, false>(s.sched, s.unit))
+                       : (h.noise ? pick<false, true>(s.sched, s.unit) : pick<false, false>(s.sched, s.unit));
     if (fn == nullptr) return hipErrorInvalidValue;
     const size_t units = step_kernel_units(s);
     const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -116,13 +122,13 @@ hipError_t launch_step(const KScene& s, const KHyper& h, bool rsr, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_rsr(const KScene& s, const KHyper& h, hipStream_t stream)
+hipError_t launch_invisible(const KScene& s, const KHyper& h, hipStream_t stream)
 {
-    if (s.n == 0 || h.rsr_thr == 0 || s.mask == nullptr) return hipSuccess;
-    const size_t units = (size_t)((s.n + kRsrUnit - 1) / kRsrUnit);
+    if (s.n == 0 || (h.rsr_thr == 0 && h.aiu_thr == 0) || s.mask == nullptr) return hipSuccess;
+    const size_t units = (size_t)((s.n + kInvUnit - 1) / kInvUnit);
     const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (s.bf16) hipLaunchKernelGGL(rsr_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
-    else hipLaunchKernelGGL(rsr_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
+    if (s.bf16) hipLaunchKernelGGL(invisible_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
+    else hipLaunchKernelGGL(invisible_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, s, h);
     return hipGetLastError();
 }
 

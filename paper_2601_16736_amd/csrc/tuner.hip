@@ -159,9 +159,9 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
         if (e != hipSuccess) break;
         s.sched = c.sched;
         s.unit = c.unit;
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(s, h, false, st);
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(s, h, st);
         (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_step(s, h, false, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_step(s, h, st);
         (void)hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;

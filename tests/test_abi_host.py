@@ -80,6 +80,9 @@ def _step(groups=None, n=10, cfg=None, **kw):
     gs.StepConfig(schedule=gs.GS_SCHED_MASKED),                # no mask
     gs.StepConfig(schedule=gs.GS_SCHED_DENSE, unit=100),       # unknown unit
     gs.StepConfig(schedule=gs.GS_SCHED_DENSE, iteration=-1),
+    gs.StepConfig(schedule=gs.GS_SCHED_DENSE, aiu_enable=True, aiu_ratio=1.5),
+    gs.StepConfig(schedule=gs.GS_SCHED_DENSE, aiu_enable=True, aiu_ratio=0.5, aiu_scale=-1.0),
+    gs.StepConfig(schedule=gs.GS_SCHED_DENSE, aiu_enable=True, aiu_ratio=0.5, aiu_scale=float("inf")),
 ])
 def test_step_rejects_bad_config(cfg):
     e = _step(cfg=cfg)
@@ -135,3 +138,76 @@ def test_tune_rejects_bad_arguments():
     for args in ((0, [3], 0.3), (100, [], 0.3), (100, [3], 0.0), (100, [3], 1.5), (100, [0], 0.3)):
         with pytest.raises(gs.GsError):
             gs.gs_tune(*args)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors have the C header's sizes and offsets
+    (a C program built against include/gsopt.h prints them)."""
+    import subprocess
+    structs = {"gs_camera": gs.gs_camera, "gs_group": gs.gs_group, "gs_step_config": gs.gs_step_config,
+               "gs_scene": gs.gs_scene}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsopt.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    for row in filter(None, out):
+        name, field, val = row.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), f"{name}.{field}: ctypes {got}, C {val}"
+
+
+def _prune(n=10, src=None, dst=None, dtype=0, keep=FAKE + 65536, t_src=FAKE + 131072, t_dst=FAKE + 196608,
+           cnt=FAKE + 262144, ws=None):
+    src = [_group(param=_Fake(FAKE, (n, 3)))] if src is None else src
+    dst = [_group(param=_Fake(FAKE + 1 << 20, (n, 3)), grad=None)] if dst is None else dst
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_prune(_Fake(keep, (n,)), src, dst, dtype, t_src, t_dst, cnt, ws, stream=0)
+    return e.value
+
+
+def test_prune_rejects_bad_arguments():
+    """Every call here fails validation before any launch."""
+    assert _prune(n=-1).status == gs.GS_EINVAL
+    assert _prune(n=2**31).status == gs.GS_EINVAL
+    assert _prune(dtype=3).status == gs.GS_EINVAL
+    assert _prune(cnt=0).status == gs.GS_EINVAL                        # kept_count NULL
+    assert _prune(cnt=FAKE + 2).status == gs.GS_EINVAL                 # misaligned
+    assert _prune(keep=0).status == gs.GS_EINVAL
+    assert _prune(t_dst=FAKE + 6).status == gs.GS_EINVAL
+    assert _prune(ws=None).status == gs.GS_EINVAL                      # workspace too small
+    small = _Fake(FAKE + (1 << 22), (8,))
+    small.numel, small.element_size = (lambda: 8), (lambda: 1)
+    assert _prune(ws=small).status == gs.GS_EINVAL
+    assert _prune(dst=[_group(param=_Fake(FAKE, (10, 4)))]).status == gs.GS_EINVAL      # dims differ
+    assert _prune(src=[_group(param=_Fake(FAKE + 2, (10, 3)))]).status == gs.GS_EINVAL  # misaligned
+    assert _prune(src=[_group(param=_Fake(FAKE, (10, 3)))] * 9,
+                  dst=[_group(param=_Fake(FAKE, (10, 3)))] * 9).status == gs.GS_EINVAL
+    with pytest.raises(ValueError):
+        gs.gs_prune(_Fake(FAKE, (10,)), [_group()], [], 0, FAKE, FAKE, FAKE, None, stream=0)
+    assert gs.gs_prune_workspace_size(0) == 0
+    assert gs.gs_prune_workspace_size(10**6) > 2 * 4 * (10**6 // 512)
+
+
+def test_append_rejects_bad_arguments():
+    def app(n=10, k=4, dtype=0, src=FAKE + 65536, t=FAKE + 131072, groups=None):
+        groups = [_group(param=_Fake(FAKE, (n + k, 3)))] if groups is None else groups
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_append(groups, dtype, n, _Fake(src, (k,)), t, stream=0)
+        return e.value
+    assert app(n=-1).status == gs.GS_EINVAL
+    assert app(n=2**31 - 2, k=4).status == gs.GS_EINVAL
+    assert app(dtype=2).status == gs.GS_EINVAL
+    assert app(src=0).status == gs.GS_EINVAL
+    assert app(t=0).status == gs.GS_EINVAL
+    assert app(t=FAKE + 2).status == gs.GS_EINVAL
+    assert app(groups=[_group(param=_Fake(FAKE, (14, 3)), exp_avg=FAKE + 1)]).status == gs.GS_EINVAL
+    assert app(groups=[]).status == gs.GS_EINVAL

@@ -40,8 +40,16 @@ SCENES = [  # (n, visible ratio, schedule, layout)
 ]
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_batched_equals_per_scene_calls(bf16):
+def _noise_kw(on):
+    # position noise on the mean group; both layouts start means, scales, quats, opacity
+    return dict(noise_enable=on, noise_groups=(0, 1, 2, 3), noise_lr=0.05 / synth.GROUPS_59[0][2], noise_k=100.0,
+                noise_t=0.5)     # opacities of these states spread around 0.5
+
+
+@pytest.mark.parametrize("bf16,noise", [(False, False), (True, False), (True, True)])
+def test_batched_equals_per_scene_calls(bf16, noise):
+    """noise=True switches position noise on every other replay, so one plan
+    runs both of its kernel variants."""
     rng = np.random.default_rng(3)
     plans, refs = [], []
     for s, (n, p, sched, spec) in enumerate(SCENES):
@@ -65,14 +73,16 @@ def test_batched_equals_per_scene_calls(bf16):
             m = synth.bernoulli_mask(d["n"], d["p"], s, it)
             d["mask"].copy_(torch.from_numpy(m))
             gs.gs_compact(d["mask"], d["idx"], d["cnt"])
+        nz = _noise_kw(noise and it % 2 == 0)
+        nz.update(aiu_enable=(it % 3 == 2), aiu_ratio=0.3, aiu_scale=0.5)     # AIU on replays 2 (and 5)
         cfg = gs.StepConfig(iteration=it, seed=77, rsr_enable=(it % 2 == 1), rsr_ratio=0.25,
-                            moment_dtype=int(bf16), stochastic_round=True)
+                            moment_dtype=int(bf16), stochastic_round=True, **nz)
         batch.step(cfg)
         torch.cuda.synchronize()
         for s, (d, r) in enumerate(zip(plans, refs)):
             sched = batch.schedule(s)
             c1 = gs.StepConfig(iteration=it, seed=77 + s, rsr_enable=(it % 2 == 1), rsr_ratio=0.25,
-                               moment_dtype=int(bf16), stochastic_round=True, schedule=sched)
+                               moment_dtype=int(bf16), stochastic_round=True, schedule=sched, **nz)
             gs.adamw_gs_step(r["groups"], d["n"], r["t"], c1, visible=d["mask"], vis_idx=d["idx"],
                              vis_count=d["cnt"])
         torch.cuda.synchronize()

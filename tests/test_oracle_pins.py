@@ -406,3 +406,265 @@ def test_bf16_sr_counts_exact():
             assert out in ((bits >> 16), (bits >> 16) + 1)
             ups += out == (bits >> 16) + 1
         assert ups == low
+
+
+# ---------------------------------------------------------------- position noise
+def test_noise_gamma_is_standard_normal():
+    """Box-Muller on the counter draws: each component N(0, 1), uncorrelated
+    (KS test against the normal CDF, moments within 5 standard errors)."""
+    from scipy import stats
+    n = 60_000
+    g = np.array([oracle.noise_gamma(3, 17, i) for i in range(n)])
+    assert np.abs(g.mean(axis=0)).max() < 5 / math.sqrt(n)
+    assert np.abs(g.var(axis=0) - 1).max() < 5 * math.sqrt(2 / n)
+    c = np.corrcoef(g.T)
+    assert np.abs(c[np.triu_indices(3, 1)]).max() < 5 / math.sqrt(n)
+    for k in range(3):
+        assert stats.kstest(g[:, k], "norm").pvalue > 1e-3
+
+
+def test_noise_displacement_against_scipy_rotation():
+    """eta_Ro * eta_mu * sigma(-k (sigma(tau) - t)) * R diag(e^{2 kappa}) R^T gamma,
+    with R from scipy's quaternion rotation (scalar-last there)."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(21)
+    cfg = oracle.Config(noise_lr=5e5, noise_k=100.0, noise_t=0.005)
+    for _ in range(50):
+        q = rng.standard_normal(4) * 3.0               # not normalised on purpose
+        kappa = rng.normal(-3.0, 1.0, 3)
+        tau = rng.normal(-4.0, 2.0)
+        gamma = rng.standard_normal(3)
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        sigma = R @ np.diag(np.exp(2 * kappa)) @ R.T
+        o = 1 / (1 + np.exp(-tau))
+        gate = 1 / (1 + np.exp(100.0 * (o - 0.005)))
+        expect = 5e5 * 1.6e-4 * gate * (sigma @ gamma)
+        np.testing.assert_allclose(oracle.noise_displacement(q, kappa, tau, 1.6e-4, cfg, gamma), expect,
+                                   rtol=1e-10, atol=1e-300)
+
+
+def test_noise_displacement_hand_cases():
+    cfg = oracle.Config(noise_lr=2.0, noise_k=10.0, noise_t=0.5)
+    tau = 0.0                                            # o = 0.5 = t: gate = 1/2
+    g = np.array([1.0, -2.0, 0.5])
+    kap = np.array([0.0, math.log(2.0), math.log(3.0)])  # S^2 = diag(1, 4, 9)
+    # identity rotation: lr * eta_Ro * 1/2 * (1, -8, 4.5)
+    np.testing.assert_allclose(oracle.noise_displacement([1, 0, 0, 0], kap, tau, 0.1, cfg, g),
+                               0.1 * 2.0 * 0.5 * np.array([1.0, -8.0, 4.5]), rtol=1e-14)
+    # 90 degrees about z: x and y scales swap -> S^2 seen as diag(4, 1, 9)
+    h = math.sqrt(0.5)
+    np.testing.assert_allclose(oracle.noise_displacement([h, 0, 0, h], kap, tau, 0.1, cfg, g),
+                               0.1 * 2.0 * 0.5 * np.array([4.0, -2.0, 4.5]), rtol=1e-13, atol=1e-15)
+    # a scaled quaternion is the same rotation
+    np.testing.assert_allclose(oracle.noise_displacement([7 * h, 0, 0, 7 * h], kap, tau, 0.1, cfg, g),
+                               oracle.noise_displacement([h, 0, 0, h], kap, tau, 0.1, cfg, g), rtol=1e-14)
+
+
+def test_noise_in_step_moves_visible_means_only():
+    n, spec = 500, synth.GROUPS_59
+    rng = np.random.default_rng(22)
+    base = []
+    for name, dim, lr, dar in spec:
+        base.append(_one_group(n, dim, lr, dar_kind=dar, lam=1e-3, clip=10.0, theta=rng.standard_normal((n, dim))))
+        base[-1].grad[:] = 1e-3 * rng.standard_normal((n, dim))
+    def copy(gs_):
+        return [oracle.Group(g.param.copy(), g.grad.copy(), g.m.copy(), g.v.copy(), g.lr, g.dar_kind, g.dar_lambda,
+                             g.dar_clip) for g in gs_]
+    a, b = copy(base), copy(base)
+    mask = (rng.random(n) < 0.5).astype(np.uint8)
+    ta, tb = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    cfg_on = oracle.Config(seed=4, iteration=9, noise_enable=True, noise_groups=(0, 1, 2, 3), noise_lr=50.0)
+    oracle.adamw_gs_step(a, n, mask, ta, cfg_on)
+    oracle.adamw_gs_step(b, n, mask, tb, oracle.Config(seed=4, iteration=9))
+    for k in range(1, 5):                                # other groups: identical
+        np.testing.assert_array_equal(a[k].param, b[k].param)
+    inv = mask == 0
+    np.testing.assert_array_equal(a[0].param[inv], base[0].param[inv])
+    for i in np.flatnonzero(mask)[:40]:
+        d = oracle.noise_displacement(base[2].param[i], base[1].param[i], base[3].param[i, 0], spec[0][2], cfg_on,
+                                      oracle.noise_gamma(4, 9, int(i)))
+        np.testing.assert_allclose(a[0].param[i], b[0].param[i] - d, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------- AIU
+def _aiu_state(n, spec, seed, lam=0.0, t_max=30):
+    """Groups with moments and step counts in use (t = 0 on some rows)."""
+    rng = np.random.default_rng(seed)
+    gr = []
+    for name, dim, lr, dar in spec:
+        g = _one_group(n, dim, lr, dar_kind=dar if lam else 0, lam=lam, clip=10.0, theta=rng.standard_normal((n, dim)))
+        g.m[:] = 1e-3 * rng.standard_normal((n, dim))
+        g.v[:] = 1e-6 * rng.random((n, dim)) + 1e-8
+        g.grad[:] = 1e-3 * rng.standard_normal((n, dim))
+        gr.append(g)
+    t = rng.integers(0, t_max, n).astype(np.int32)
+    return gr, t
+
+
+def _copy_groups(gs_):
+    return [oracle.Group(g.param.copy(), g.grad.copy(), g.m.copy(), g.v.copy(), g.lr, g.dar_kind, g.dar_lambda,
+                         g.dar_clip, g.reg_mode) for g in gs_]
+
+
+def test_aiu_repeats_the_last_visible_update():
+    """A primitive visible at one step and AIU-sampled (Pro = 1, eta = 1) at
+    the next, invisible one, moves again by exactly the update it just made:
+    AIU takes the Adam direction of the unchanged moments with the same step
+    count.  eta_AIU scales it; moments and t do not change."""
+    n, spec = 300, synth.GROUPS_59
+    g, t = _aiu_state(n, spec, 31)
+    t[:] = np.maximum(t, 1)
+    ones = np.ones(n, np.uint8)
+    zeros = np.zeros(n, np.uint8)
+    for scale in (1.0, 0.25):
+        a, ta = _copy_groups(g), t.copy()
+        oracle.adamw_gs_step(a, n, ones, ta, oracle.Config(seed=1, iteration=5))
+        delta = [x.param - y.param for x, y in zip(a, g)]
+        mid = _copy_groups(a)
+        tb = ta.copy()
+        oracle.adamw_gs_step(a, n, zeros, tb, oracle.Config(seed=1, iteration=6, aiu_enable=True, aiu_ratio=1.0,
+                                                            aiu_scale=scale))
+        np.testing.assert_array_equal(tb, ta)
+        for x, y, d in zip(a, mid, delta):
+            np.testing.assert_array_equal(x.m, y.m)
+            np.testing.assert_array_equal(x.v, y.v)
+            np.testing.assert_allclose(x.param - y.param, scale * d, rtol=1e-9, atol=1e-15)
+
+
+def test_aiu_carries_no_regulariser_term():
+    """With DAR on, the visible update holds the DAR term but the AIU update
+    is the Adam direction alone (the step without DAR)."""
+    n, spec = 200, synth.GROUPS_59
+    g, t = _aiu_state(n, spec, 32, lam=50.0)
+    t[:] = np.maximum(t, 1)
+    plain = _copy_groups(g)
+    for x in plain:
+        x.dar_kind, x.dar_lambda = 0, 0.0
+    ones = np.ones(n, np.uint8)
+    a, ta = _copy_groups(g), t.copy()
+    b, tb = _copy_groups(plain), t.copy()
+    oracle.adamw_gs_step(a, n, ones, ta, oracle.Config(seed=2, iteration=1))
+    oracle.adamw_gs_step(b, n, ones, tb, oracle.Config(seed=2, iteration=1))
+    d_plain = [y.param - x.param for x, y in zip(plain, b)]
+    assert any(np.abs((y.param - x.param) - d).max() > 1e-6 for x, y, d in zip(g, a, d_plain))   # DAR acted
+    mid = _copy_groups(a)
+    oracle.adamw_gs_step(a, n, np.zeros(n, np.uint8), ta,
+                         oracle.Config(seed=2, iteration=2, aiu_enable=True, aiu_ratio=1.0, aiu_scale=1.0))
+    for x, y, d in zip(a, mid, d_plain):
+        np.testing.assert_allclose(x.param - y.param, d, rtol=1e-9, atol=1e-15)
+
+
+def test_aiu_samples_invisible_rows_with_moments_only():
+    """Only invisible, sampled rows with t > 0 move; the sampled fraction is
+    Pro_AIU within binomial bounds; visible rows are those of the step
+    without AIU, bit for bit."""
+    n, spec, p = 20_000, [("a", 2, 0.1, 0), ("b", 1, 0.2, 0)], 0.3
+    g, t = _aiu_state(n, spec, 33)
+    mask = (np.random.default_rng(34).random(n) < 0.4).astype(np.uint8)
+    a, ta = _copy_groups(g), t.copy()
+    b, tb = _copy_groups(g), t.copy()
+    cfg = oracle.Config(seed=9, iteration=3, aiu_enable=True, aiu_ratio=p, aiu_scale=0.5)
+    oracle.adamw_gs_step(a, n, mask, ta, cfg)
+    oracle.adamw_gs_step(b, n, mask, tb, oracle.Config(seed=9, iteration=3))
+    np.testing.assert_array_equal(ta, tb)
+    vis = mask == 1
+    moved = np.any(a[0].param != b[0].param, axis=1)
+    assert not moved[vis].any()
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.param[vis], y.param[vis])
+        np.testing.assert_array_equal(x.m, y.m)
+        np.testing.assert_array_equal(x.v, y.v)
+    sampled = oracle.aiu_sample_mask(9, 3, n, p)
+    np.testing.assert_array_equal(moved, ~vis & sampled & (t > 0))
+    k, m = int(sampled.sum()), n
+    assert abs(k - p * m) < 5 * math.sqrt(m * p * (1 - p))
+    # an independent stream: the Re-State sample of the same iteration differs
+    assert (sampled != oracle.rsr_sample_mask(9, 3, n, p)).sum() > 0.2 * n
+
+
+def test_aiu_reads_the_rescaled_moments():
+    """AIU and Re-State in one iteration: the extra update uses the moments
+    after the rescale, so with alpha1 = 0.5, alpha2 = 0.04 (not alpha1^2) the
+    direction grows by alpha1 / sqrt(alpha2) = 2.5."""
+    n, spec = 100, [("a", 3, 0.1, 0)]
+    g, t = _aiu_state(n, spec, 35)
+    t[:] = np.maximum(t, 1)
+    zeros = np.zeros(n, np.uint8)
+    a, b = _copy_groups(g), _copy_groups(g)
+    oracle.adamw_gs_step(a, n, zeros, t.copy(), oracle.Config(seed=3, iteration=4, aiu_enable=True, aiu_ratio=1.0,
+                                                               aiu_scale=1.0))
+    oracle.adamw_gs_step(b, n, zeros, t.copy(), oracle.Config(seed=3, iteration=4, aiu_enable=True, aiu_ratio=1.0,
+                                                               aiu_scale=1.0, rsr_enable=True, rsr_ratio=1.0,
+                                                               rsr_alpha1=0.5, rsr_alpha2=0.04))
+    np.testing.assert_allclose(b[0].param - g[0].param, 2.5 * (a[0].param - g[0].param), rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(b[0].m, 0.5 * g[0].m, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- primitive-set mutation
+def test_prune_is_boolean_row_selection():
+    """Pruning keeps the rows with keep != 0 in order: numpy's boolean
+    indexing of every array, including the step counts."""
+    rng = np.random.default_rng(40)
+    n, spec = 1000, synth.GROUPS_59
+    g, t = _aiu_state(n, spec, 41)
+    for p in (0.0, 0.3, 1.0):
+        keep = (rng.random(n) < p).astype(np.uint8)
+        d, td = oracle.prune(g, keep, t)
+        np.testing.assert_array_equal(td, t[keep == 1])
+        for x, y in zip(d, g):
+            np.testing.assert_array_equal(x.param, y.param[keep == 1])
+            np.testing.assert_array_equal(x.m, y.m[keep == 1])
+            np.testing.assert_array_equal(x.v, y.v[keep == 1])
+
+
+def test_prune_commutes_with_the_step():
+    """The optimizer state travels with its primitive: pruning then stepping
+    the kept rows gives what stepping then pruning gives (no Re-State, whose
+    draws are keyed by the scene index)."""
+    rng = np.random.default_rng(42)
+    n, spec = 500, synth.GROUPS_59
+    g, t = _aiu_state(n, spec, 43, lam=1e-3)
+    keep = (rng.random(n) < 0.6).astype(np.uint8)
+    vis = (rng.random(n) < 0.5).astype(np.uint8)
+    a, ta = _copy_groups(g), t.copy()
+    oracle.adamw_gs_step(a, n, vis, ta, oracle.Config(iteration=3))
+    a, ta = oracle.prune(a, keep, ta)
+    b, tb = oracle.prune(_copy_groups(g), keep, t.copy())
+    for x, y in zip(b, g):                     # gradients belong to the iteration: the caller's
+        x.grad = np.ascontiguousarray(y.grad[keep == 1])
+    kv = np.ascontiguousarray(vis[keep == 1])
+    oracle.adamw_gs_step(b, b[0].param.shape[0], kv, tb, oracle.Config(iteration=3))
+    np.testing.assert_array_equal(ta, tb)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.param, y.param)
+        np.testing.assert_array_equal(x.m, y.m)
+
+
+def test_append_gives_clones_with_a_fresh_state():
+    """New rows copy their source's attributes with m = v = 0 and t = 0 (RSR
+    with alpha = 0, plus a new step count); their first visible step is then
+    Adam's first step, theta - lr g / (|g| + eps) (Kingma & Ba); old rows
+    do not change."""
+    n, k, spec = 400, 150, synth.GROUPS_59
+    g, t = _aiu_state(n + k, spec, 44)
+    rng = np.random.default_rng(45)
+    src = rng.integers(0, n, k).astype(np.int64)
+    before = _copy_groups(g)
+    t0 = t.copy()
+    oracle.append(g, n, src, t)
+    np.testing.assert_array_equal(t[:n], t0[:n])
+    assert (t[n:] == 0).all()
+    for x, y in zip(g, before):
+        np.testing.assert_array_equal(x.param[:n], y.param[:n])
+        np.testing.assert_array_equal(x.m[:n], y.m[:n])
+        np.testing.assert_array_equal(x.param[n:], y.param[src])
+        assert (x.m[n:] == 0).all() and (x.v[n:] == 0).all()
+    vis = np.zeros(n + k, np.uint8)
+    vis[n:] = 1
+    new = _copy_groups(g)
+    oracle.adamw_gs_step(g, n + k, vis, t, oracle.Config(iteration=1, eps=1e-15))
+    for x, y in zip(g, new):
+        gr = y.grad[n:]
+        np.testing.assert_allclose(x.param[n:], y.param[n:] - y.lr * gr / (np.abs(gr) + 1e-15), rtol=1e-12,
+                                   atol=1e-15)
+    assert (t[n:] == 1).all()
