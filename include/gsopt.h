@@ -101,6 +101,21 @@ gs_status gs_visibility(const float* means, const float* radius, int64_t n,
                         int32_t* vis_count, hipStream_t stream);
 
 /*
+ * Several views in one pass (a batch of training views; the paper trains on
+ * one view per iteration and is silent on batches).  The predicate above is
+ * evaluated for each of the n_cams (1..32) cameras:
+ * view_bits [n] uint32 out, bit v = visible in cams[v], or NULL;
+ * mask      [n] uint8 out, 1 where any view sees the primitive (the union, the
+ *           V of a step over the batch), or NULL;
+ * vis_idx / vis_count: the union's indices, as for gs_visibility, or NULL.
+ * At least one output must be non-NULL.  cams is a host array.
+ */
+gs_status gs_visibility_multi(const float* means, const float* radius, int64_t n,
+                              const gs_camera* cams, int32_t n_cams, uint8_t* mask,
+                              uint32_t* view_bits, int32_t* vis_idx, int32_t* vis_count,
+                              hipStream_t stream);
+
+/*
  * Compaction alone: vis_idx/vis_count from an existing mask ([n] uint8,
  * nonzero = visible).  Same output contract as gs_visibility.
  */

@@ -91,6 +91,7 @@ def lib():
         L.orc_visible_f32.restype = ctypes.c_int; L.orc_visible_f32.argtypes = [vp, vp, vp]
         L.orc_visibility.restype = None; L.orc_visibility.argtypes = [vp, vp, i64, vp, vp]
         L.orc_visibility_f64.restype = None; L.orc_visibility_f64.argtypes = [vp, vp, i64, vp, vp]
+        L.orc_visibility_multi.restype = None; L.orc_visibility_multi.argtypes = [vp, vp, i64, vp, i32, vp, vp]
         L.orc_compact.restype = i64; L.orc_compact.argtypes = [vp, i64, vp]
         L.orc_adamw_gs_step.restype = None; L.orc_adamw_gs_step.argtypes = [vp, i32, i64, vp, vp, vp]
         L.orc_adamw_gs_step_rows.restype = None
@@ -209,6 +210,22 @@ def visibility(means: np.ndarray, cam: Camera, radius: Optional[np.ndarray] = No
     c = cam._c()
     lib().orc_visibility(_ptr(means), _ptr(radius), n, ctypes.addressof(c), _ptr(mask))
     return mask
+
+
+def visibility_multi(means: np.ndarray, cams: List[Camera], radius: Optional[np.ndarray] = None):
+    """(union mask uint8, per-view bits uint32) over up to 32 views."""
+    means = _need(np.ascontiguousarray(means), np.float32)
+    n = means.shape[0]
+    if radius is not None:
+        radius = _need(np.ascontiguousarray(radius), np.float32)
+    if not 1 <= len(cams) <= 32:
+        raise ValueError("1..32 views")
+    arr = (type(cams[0]._c()) * len(cams))(*[c._c() for c in cams])
+    mask = np.zeros(n, np.uint8)
+    bits = np.zeros(n, np.uint32)
+    lib().orc_visibility_multi(_ptr(means), _ptr(radius), n, ctypes.addressof(arr), len(cams), _ptr(mask),
+                               _ptr(bits))
+    return mask, bits
 
 
 def visibility_f64(means: np.ndarray, cam: Camera, radius: Optional[np.ndarray] = None) -> np.ndarray:

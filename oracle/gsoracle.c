@@ -172,6 +172,21 @@ void orc_visibility(const float* means, const float* radius, int64_t n,
         mask[i] = (uint8_t)orc_visible_f32(means + 3 * i, radius ? radius + i : NULL, cam);
 }
 
+/* Several views at once (a batch of training views): bit v of bits[i] is
+ * primitive i's predicate in view v (n_cams <= 32), and the union mask is 1
+ * where any bit is set.  Either output may be NULL. */
+void orc_visibility_multi(const float* means, const float* radius, int64_t n, const orc_camera* cams,
+                          int32_t n_cams, uint8_t* mask, uint32_t* bits)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t b = 0;
+        for (int32_t v = 0; v < n_cams; ++v)
+            if (orc_visible_f32(means + 3 * i, radius ? radius + i : NULL, &cams[v])) b |= 1u << v;
+        if (bits) bits[i] = b;
+        if (mask) mask[i] = (uint8_t)(b != 0);
+    }
+}
+
 /* Same predicate in FP64: a diagnostic only (the mask is defined in FP32).  */
 void orc_visibility_f64(const float* means, const float* radius, int64_t n,
                         const orc_camera* c, uint8_t* mask)

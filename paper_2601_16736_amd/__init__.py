@@ -91,6 +91,8 @@ _lib.gs_reg_norm.restype = ctypes.c_double
 _lib.gs_reg_norm.argtypes = [ctypes.c_double]
 _lib.gs_visibility.restype = _i32
 _lib.gs_visibility.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
+_lib.gs_visibility_multi.restype = _i32
+_lib.gs_visibility_multi.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.gs_compact.restype = _i32
 _lib.gs_compact.argtypes = [_vp, _i64, _vp, _vp, _vp]
 _lib.adamw_gs_step.restype = _i32
@@ -128,8 +130,8 @@ _lib.gs_prune.argtypes = [_vp, _i64, ctypes.POINTER(gs_group), ctypes.POINTER(gs
 _lib.gs_append.restype = _i32
 _lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64, _vp, _vp]
 
-EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_compact", "adamw_gs_step",
-            "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
+EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_visibility_multi", "gs_compact",
+            "adamw_gs_step", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
             "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
             "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
             "gs_prune", "gs_append"]
@@ -203,6 +205,15 @@ def gs_visibility(means, cam: Camera, mask=None, vis_idx=None, vis_count=None, r
     c = cam.to_c()
     _check(_lib.gs_visibility(_ptr(means), _ptr(radius), n, ctypes.byref(c), _ptr(mask), _ptr(vis_idx),
                               _ptr(vis_count), _stream(stream)))
+
+
+def gs_visibility_multi(means, cams: Sequence[Camera], mask=None, view_bits=None, vis_idx=None, vis_count=None,
+                        radius=None, stream=None) -> None:
+    """Up to 32 views at once: per-view bits (uint32 as int32 tensor), union mask, union indices."""
+    n = int(means.shape[0])
+    arr = (gs_camera * max(len(cams), 1))(*[c.to_c() for c in cams])
+    _check(_lib.gs_visibility_multi(_ptr(means), _ptr(radius), n, arr, len(cams), _ptr(mask), _ptr(view_bits),
+                                    _ptr(vis_idx), _ptr(vis_count), _stream(stream)))
 
 
 def gs_compact(mask, vis_idx, vis_count, stream=None) -> None:

@@ -262,6 +262,30 @@ double gs_reg_norm(double n_pixels)
     return (double)((v / p) * p) / 10.0;
 }
 
+// Validates a camera and fills its kernel view (prefix names it in messages).
+static gs_status to_kcamera(const gs_camera* cam, KCamera* k, const char* prefix)
+{
+    if (cam->width < 1 || cam->height < 1) return fail(GS_EINVAL, "%scamera width/height must be >= 1", prefix);
+    if (!(cam->z_near >= 0.0f) || !(cam->z_far > cam->z_near))
+        return fail(GS_EINVAL, "%scamera needs 0 <= z_near < z_far", prefix);
+    for (int j = 0; j < 12; ++j)
+        if (!std::isfinite(cam->view[j])) return fail(GS_EINVAL, "%scamera view matrix must be finite", prefix);
+    if (!std::isfinite(cam->fx) || !std::isfinite(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+        return fail(GS_EINVAL, "%scamera intrinsics must be finite", prefix);
+    memcpy(k->R, cam->view, sizeof k->R);
+    k->fx = cam->fx;
+    k->fy = cam->fy;
+    k->cx = cam->cx;
+    k->cy = cam->cy;
+    k->W = (float)cam->width;
+    k->H = (float)cam->height;
+    k->z_near = cam->z_near;
+    k->z_far = cam->z_far;
+    k->r_min = cam->r_min_px;
+    k->f_max = cam->fx > cam->fy ? cam->fx : cam->fy;
+    return GS_OK;
+}
+
 gs_status gs_visibility(const float* means, const float* radius, int64_t n, const gs_camera* cam, uint8_t* mask,
                         int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
 {
@@ -273,27 +297,39 @@ gs_status gs_visibility(const float* means, const float* radius, int64_t n, cons
     if (n > 0 && means == nullptr) return fail(GS_EINVAL, "means is NULL");
     if (!aligned(means, 4) || !aligned(radius, 4) || !aligned(vis_idx, 4) || !aligned(vis_count, 4))
         return fail(GS_EINVAL, "misaligned pointer (4-byte alignment required)");
-    if (cam->width < 1 || cam->height < 1) return fail(GS_EINVAL, "camera width/height must be >= 1");
-    if (!(cam->z_near >= 0.0f) || !(cam->z_far > cam->z_near))
-        return fail(GS_EINVAL, "camera needs 0 <= z_near < z_far");
-    for (int k = 0; k < 12; ++k)
-        if (!std::isfinite(cam->view[k])) return fail(GS_EINVAL, "camera view matrix must be finite");
-    if (!std::isfinite(cam->fx) || !std::isfinite(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
-        return fail(GS_EINVAL, "camera intrinsics must be finite");
     KCamera k;
-    memcpy(k.R, cam->view, sizeof k.R);
-    k.fx = cam->fx;
-    k.fy = cam->fy;
-    k.cx = cam->cx;
-    k.cy = cam->cy;
-    k.W = (float)cam->width;
-    k.H = (float)cam->height;
-    k.z_near = cam->z_near;
-    k.z_far = cam->z_far;
-    k.r_min = cam->r_min_px;
-    k.f_max = cam->fx > cam->fy ? cam->fx : cam->fy;
+    const gs_status st = to_kcamera(cam, &k, "");
+    if (st != GS_OK) return st;
     const hipError_t e = launch_visibility(means, radius, n, k, mask, vis_idx, vis_count, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_visibility launch");
+}
+
+gs_status gs_visibility_multi(const float* means, const float* radius, int64_t n, const gs_camera* cams,
+                              int32_t n_cams, uint8_t* mask, uint32_t* view_bits, int32_t* vis_idx,
+                              int32_t* vis_count, hipStream_t stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    if (cams == nullptr) return fail(GS_EINVAL, "cams is NULL");
+    if (n_cams < 1 || n_cams > kMaxViews) return fail(GS_EINVAL, "n_cams = %d, must be in [1, %d]", n_cams, kMaxViews);
+    if (mask == nullptr && view_bits == nullptr && vis_idx == nullptr)
+        return fail(GS_EINVAL, "mask, view_bits and vis_idx are all NULL");
+    if (vis_idx != nullptr && vis_count == nullptr) return fail(GS_EINVAL, "vis_idx needs vis_count");
+    if (n > 0 && means == nullptr) return fail(GS_EINVAL, "means is NULL");
+    if (!aligned(means, 4) || !aligned(radius, 4) || !aligned(view_bits, 4) || !aligned(vis_idx, 4) ||
+        !aligned(vis_count, 4))
+        return fail(GS_EINVAL, "misaligned pointer (4-byte alignment required)");
+    KCameras k;
+    memset(&k, 0, sizeof k);
+    for (int v = 0; v < n_cams; ++v) {
+        char prefix[32];
+        snprintf(prefix, sizeof prefix, "view %d: ", v);
+        const gs_status st = to_kcamera(&cams[v], &k.c[v], prefix);
+        if (st != GS_OK) return st;
+    }
+    k.n = n_cams;
+    const hipError_t e = launch_visibility_multi(means, radius, n, k, mask, view_bits, vis_idx, vis_count, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_visibility_multi launch");
 }
 
 gs_status gs_compact(const uint8_t* mask, int64_t n, int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)

@@ -81,11 +81,20 @@ struct KCamera {
     float r_min, f_max;
 };
 
+// up to 32 views for the multi-view visibility pass (kernel argument)
+constexpr int kMaxViews = 32;
+struct KCameras {
+    KCamera c[kMaxViews];
+    int32_t n;
+};
+
 // host-side helpers shared by the library's translation units
 uint64_t splitmix_output(uint64_t s, uint64_t k);
 
 hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
                              uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream);
+hipError_t launch_visibility_multi(const float* means, const float* radius, int64_t n, const KCameras& cams,
+                                   uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count, hipStream_t stream);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream);
 // The invisible-row pass (Re-State / AIU samples) runs first when either is on.
 hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream);

@@ -110,6 +110,48 @@ __global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restr
     if (idx != nullptr) block_append(vis, first, idx, count);
 }
 
+// Several views in one pass: bit v of a primitive's word is its predicate in
+// view v; the union (any bit) feeds the mask and the index list.  The means
+// are read once for all views.
+template <bool RADIUS>
+__global__ __launch_bounds__(kBlock) void visibility_multi_kernel(const float* __restrict__ means,
+                                                                  const float* __restrict__ radius, int64_t n,
+                                                                  KCameras cams, uint8_t* __restrict__ mask,
+                                                                  uint32_t* __restrict__ bits,
+                                                                  int32_t* __restrict__ idx, int32_t* count)
+{
+    const int64_t first = (int64_t)blockIdx.x * kVisPerBlock;
+    float x[kVisRounds], y[kVisRounds], z[kVisRounds], rho[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        const int64_t i = min(first + s * kBlock + threadIdx.x, n - 1);
+        x[s] = means[3 * i];
+        y[s] = means[3 * i + 1];
+        z[s] = means[3 * i + 2];
+        rho[s] = RADIUS ? radius[i] : 0.0f;
+    }
+    uint32_t b[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) b[s] = 0u;
+    for (int v = 0; v < cams.n; ++v) {
+        const KCamera& c = cams.c[v];
+#pragma unroll
+        for (int s = 0; s < kVisRounds; ++s)
+            if (visible_pred(x[s], y[s], z[s], RADIUS ? &rho[s] : nullptr, c)) b[s] |= 1u << v;
+    }
+    bool vis[kVisRounds];
+#pragma unroll
+    for (int s = 0; s < kVisRounds; ++s) {
+        const int64_t i = first + s * kBlock + threadIdx.x;
+        vis[s] = i < n && b[s] != 0u;
+        if (i < n) {
+            if (mask != nullptr) mask[i] = (uint8_t)vis[s];
+            if (bits != nullptr) bits[i] = b[s];
+        }
+    }
+    if (idx != nullptr) block_append(vis, first, idx, count);
+}
+
 __global__ __launch_bounds__(kBlock) void compact_kernel(const uint8_t* __restrict__ mask, int64_t n,
                                                          int32_t* __restrict__ idx, int32_t* count)
 {
@@ -156,6 +198,25 @@ hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t*
     if (e != hipSuccess || n == 0) return e;
     const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
     hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kBlock), 0, stream, mask, n, idx, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_visibility_multi(const float* means, const float* radius, int64_t n, const KCameras& cams,
+                                   uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count, hipStream_t stream)
+{
+    if (idx != nullptr) {
+        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kWave), 0, stream, count);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
+    if (radius != nullptr)
+        hipLaunchKernelGGL(visibility_multi_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n,
+                           cams, mask, bits, idx, count);
+    else
+        hipLaunchKernelGGL(visibility_multi_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n,
+                           cams, mask, bits, idx, count);
     return hipGetLastError();
 }
 

@@ -165,6 +165,25 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got == int(val), f"{name}.{field}: ctypes {got}, C {val}"
 
 
+def test_visibility_multi_rejects_bad_arguments():
+    """Every call here fails validation before any launch."""
+    cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
+    bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000, z_near=5, z_far=5)
+    means = _Fake(FAKE, (10, 3))
+    for cams, kw in (([cam], {}),                                            # no output
+                     ([], dict(mask=FAKE + 4096)),                           # no view
+                     ([cam] * 33, dict(mask=FAKE + 4096)),                   # too many views
+                     ([cam], dict(vis_idx=FAKE + 8192)),                     # idx without count
+                     ([cam], dict(view_bits=FAKE + 4098)),                   # misaligned bits
+                     ([cam, bad], dict(mask=FAKE + 4096))):                  # second view invalid
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_visibility_multi(means, cams, stream=0, **kw)
+        assert e.value.status == gs.GS_EINVAL
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_visibility_multi(means, [cam, bad], mask=FAKE + 4096, stream=0)
+    assert "view 1" in str(e.value)
+
+
 def _prune(n=10, src=None, dst=None, dtype=0, keep=FAKE + 65536, t_src=FAKE + 131072, t_dst=FAKE + 196608,
            cnt=FAKE + 262144, ws=None):
     src = [_group(param=_Fake(FAKE, (n, 3)))] if src is None else src

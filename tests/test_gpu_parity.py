@@ -97,6 +97,63 @@ def test_visibility_mask_only_and_index_only():
     np.testing.assert_array_equal(np.sort(idx.cpu().numpy()[:int(cnt.item())]), np.flatnonzero(ref))
 
 
+@pytest.mark.parametrize("n", [0, 1, 1025, 100_003])
+@pytest.mark.parametrize("views", [1, 3, 8, 32])
+@pytest.mark.parametrize("with_radius", [False, True])
+def test_visibility_multi_bit_exact(n, views, with_radius):
+    """Per-view bits, union mask and union index set against the oracle, bit
+    for bit (n spans several blocks and a ragged tail)."""
+    means = _boundary_means(n, 4)
+    radius = (synth.rng(5, 51).random(n) * 0.5).astype(np.float32) if with_radius else None
+    rig = _cams()
+    cams = [rig[(37 * v) % 200] for v in range(views)]
+    kw = {"r_min": 0.5} if with_radius else {}
+    d_means = torch.from_numpy(means).to(DEV)
+    d_rad = torch.from_numpy(radius).to(DEV) if with_radius else None
+    m = max(n, 1)
+    mask = torch.full((m,), 7, dtype=torch.uint8, device=DEV)
+    bits = torch.full((m,), -1, dtype=torch.int32, device=DEV)
+    idx = torch.full((m,), -1, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), 12345, dtype=torch.int32, device=DEV)
+    print(f"visibility_multi n={n} views={views} radius={with_radius}", flush=True)
+    gs.gs_visibility_multi(d_means, [_gcam(c, **kw) for c in cams], mask=mask, view_bits=bits, vis_idx=idx,
+                           vis_count=cnt, radius=d_rad)
+    torch.cuda.synchronize()
+    ref_mask, ref_bits = oracle.visibility_multi(means, [_ocam(c, **kw) for c in cams], radius)
+    np.testing.assert_array_equal(mask.cpu().numpy()[:n], ref_mask)
+    np.testing.assert_array_equal(bits.cpu().numpy().view(np.uint32)[:n], ref_bits)
+    k = int(cnt.item())
+    assert k == int(ref_mask.sum())
+    np.testing.assert_array_equal(np.sort(idx.cpu().numpy()[:k]), np.flatnonzero(ref_mask))
+    if n and views == 1:           # one view: the single-view call's mask
+        single = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        gs.gs_visibility(d_means, _gcam(cams[0], **kw), mask=single, radius=d_rad)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(single.cpu().numpy(), ref_mask)
+
+
+def test_visibility_multi_outputs_alone_and_rejects_bad_views():
+    n = 20_000
+    means = _boundary_means(n, 6)
+    cams = [_cams()[v] for v in (3, 90, 150)]
+    d_means = torch.from_numpy(means).to(DEV)
+    ref_mask, ref_bits = oracle.visibility_multi(means, [_ocam(c) for c in cams])
+    bits = torch.zeros(n, dtype=torch.int32, device=DEV)
+    gs.gs_visibility_multi(d_means, [_gcam(c) for c in cams], view_bits=bits)
+    idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    gs.gs_visibility_multi(d_means, [_gcam(c) for c in cams], vis_idx=idx, vis_count=cnt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bits.cpu().numpy().view(np.uint32), ref_bits)
+    np.testing.assert_array_equal(np.sort(idx.cpu().numpy()[:int(cnt.item())]), np.flatnonzero(ref_mask))
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility_multi(d_means, [_gcam(cams[0])] * 33, view_bits=bits)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility_multi(d_means, [], view_bits=bits)
+    with pytest.raises(gs.GsError):
+        gs.gs_visibility_multi(d_means, [_gcam(cams[0])])
+
+
 @pytest.mark.parametrize("p", [0.0, 0.02, 0.3, 1.0])
 @pytest.mark.parametrize("n", [1, 1000, 77_777])
 def test_compact_matches_nonzero(p, n):

@@ -349,6 +349,50 @@ def test_visibility_mirror_symmetry_and_f64_agreement():
     assert (m32 != m64).sum() <= 2      # flips only at the boundary
 
 
+def test_visibility_two_opposite_views_union_closed_form():
+    """The axis camera and its mirror (at z = +15 looking down -z), no far
+    plane, means ~ U[-10,10]^3: a point is in the union iff
+    |x|, |y| <= (15 + |z|) / sqrt 3, so with a = 10 sqrt 3 - 15,
+    P = (1/10)[((10 sqrt 3)^3 - 15^3)/900 + (10 - a)] = 0.9703."""
+    a = 10 * math.sqrt(3) - 15
+    expect = (((10 * math.sqrt(3)) ** 3 - 15 ** 3) / 900 + (10 - a)) / 10
+    assert expect == pytest.approx(0.9703, abs=1e-4)
+    front = _axis_camera()
+    f = 500.0 / math.tan(math.radians(30.0))
+    back = oracle.Camera(np.array([[1, 0, 0, 0], [0, -1, 0, 0], [0, 0, -1, 15.0]], np.float32), f, f, 500.0, 500.0,
+                         1000, 1000, 0.2, float("inf"))
+    n = 400_000
+    mu = synth.rng(15).uniform(-10, 10, (n, 3)).astype(np.float32)
+    mask, bits = oracle.visibility_multi(mu, [front, back])
+    assert abs(mask.mean() - expect) < 5 * math.sqrt(expect * (1 - expect) / n)
+    # each bit is that view's own mask, in list order
+    np.testing.assert_array_equal(bits & 1, oracle.visibility(mu, front))
+    np.testing.assert_array_equal((bits >> 1) & 1, oracle.visibility(mu, back))
+    np.testing.assert_array_equal(mask, (bits != 0).astype(np.uint8))
+
+
+def test_visibility_multi_bit_order_and_rig():
+    """Bits follow the camera list (a reversed list reverses them); the rig's
+    200 views all see the origin, and a far point is seen by none."""
+    cams = [oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+            for c in synth.camera_rig()]
+    mu = synth.rng(16).uniform(-10, 10, (3000, 3)).astype(np.float32)
+    sub = cams[:32:3]
+    _, b = oracle.visibility_multi(mu, sub)
+    _, r = oracle.visibility_multi(mu, sub[::-1])
+    k = len(sub)
+    rev = np.zeros_like(b)
+    for v in range(k):
+        rev |= ((b >> v) & 1) << (k - 1 - v)
+    np.testing.assert_array_equal(r, rev)
+    pts = np.array([[0, 0, 0], [1e6, 0, 0]], np.float32)
+    for start in range(0, 200, 32):
+        m, bb = oracle.visibility_multi(pts, cams[start:start + 32])
+        width = len(cams[start:start + 32])
+        assert bb[0] == (1 << width) - 1 and bb[1] == 0
+        assert m.tolist() == [1, 0]
+
+
 def test_compaction_is_sorted_nonzero():
     mask = (synth.rng(13).random(10_001) < 0.27).astype(np.uint8)
     np.testing.assert_array_equal(oracle.compact(mask), np.flatnonzero(mask))
