@@ -61,6 +61,49 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")
 STEP_KERNEL_SOURCES = ("internal.h", "device_common.h", "step.hip")
 
 
+class TimingEvents:
+    """Pairs of HIP events for timing kernels on a stream.  They are created
+    with hipEventDisableSystemFence: a default timing event writes back and
+    invalidates the caches at each record, which costs several microseconds
+    between back-to-back kernels and would be charged to the step being
+    timed.  Read them only after a device synchronization."""
+
+    FLAGS = 0x20000000            # hipEventDisableSystemFence (hip_runtime_api.h)
+
+    def __init__(self, count: int):
+        import ctypes
+        import torch  # noqa: F401  (its HIP runtime is the one loaded)
+        self._hip = ctypes.CDLL("libamdhip64.so.7")
+        self._hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self._hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self._hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self._hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self._ctypes = ctypes
+        self.start, self.end = [], []
+        for lst in (self.start, self.end):
+            for _ in range(count):
+                e = ctypes.c_void_p()
+                if self._hip.hipEventCreateWithFlags(ctypes.byref(e), self.FLAGS) != 0:
+                    raise RuntimeError("hipEventCreateWithFlags failed")
+                lst.append(e)
+
+    def record(self, which: str, slot: int, stream) -> None:
+        ev = (self.start if which == "start" else self.end)[slot]
+        if self._hip.hipEventRecord(ev, self._ctypes.c_void_p(int(stream.cuda_stream))) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def ms(self, slot: int) -> float:
+        out = self._ctypes.c_float()
+        if self._hip.hipEventElapsedTime(self._ctypes.byref(out), self.start[slot], self.end[slot]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+    def close(self) -> None:
+        for e in self.start + self.end:
+            self._hip.hipEventDestroy(e)
+        self.start, self.end = [], []
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in STEP_KERNEL_SOURCES:
@@ -173,8 +216,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
     means = groups[0].param
     stream = torch.cuda.current_stream()
-    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev = TimingEvents(steps)
     mom = gs.GS_MOMENT_BF16 if moments == "bf16" else gs.GS_MOMENT_F32
 
     def one_step(k: int, slot: int = -1):
@@ -186,10 +228,10 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
                             rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, moment_dtype=mom,
                             stochastic_round=True, **STEP_LAUNCH)
         if slot >= 0:
-            ev_s[slot].record(stream)
+            ev.record("start", slot, stream)
         gs.adamw_gs_step(groups, N_PRIMS, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
         if slot >= 0:
-            ev_e[slot].record(stream)
+            ev.record("end", slot, stream)
 
     for k in range(warmup):
         one_step(k)
@@ -201,7 +243,8 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     wall = time.perf_counter() - t0
 
     nv = counts.cpu().numpy()[warmup:].astype(np.int64)
-    durs = np.array([ev_s[j].elapsed_time(ev_e[j]) for j in range(steps)]) * 1e-3
+    durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+    ev.close()
     plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
     step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments]
     achieved = float(step_bytes.sum() / durs[plain].sum()) / 1e9 if plain.any() else float("nan")
@@ -344,7 +387,7 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
     order = synth.camera_order(len(cams), warmup + steps, seed=3)
     gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev = TimingEvents(steps)
 
     def one(k, slot=-1):
         cnt = counts[k:k + 1]
@@ -356,10 +399,10 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
                                                      rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **STEP_LAUNCH),
                          visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
         if slot >= 0:
-            ev[slot][0].record(stream)
+            ev.record("start", slot, stream)
         gs.gs_relocate_reset(opacity, k_reloc, groups, gs.GS_MOMENT_F32, t, True, rws, stream=stream)
         if slot >= 0:
-            ev[slot][1].record(stream)
+            ev.record("end", slot, stream)
 
     for k in range(warmup):
         one(k)
@@ -370,7 +413,8 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nv = counts.cpu().numpy()[warmup:].astype(np.int64)
-    reloc_us = float(np.mean([a.elapsed_time(b) for a, b in ev]) * 1e3)
+    reloc_us = float(np.mean([ev.ms(j) for j in range(steps)]) * 1e3)
+    ev.close()
     del groups, params, grads, t, mask, idx, rws
     torch.cuda.empty_cache()
     return {"workload": "6M primitives, 64-cluster mixture means (sigma 1.5), lambda_o = lambda_s = 0.01, "

@@ -30,6 +30,9 @@ namespace {
 constexpr int kMaxScenes = kWave;     // one lane per scene when counting units
 constexpr int kBatchCap = 512;
 constexpr int kInvWindow = 512;
+// items per lane per trip in the step units: the persistent kernel keeps its
+// register budget at two (four would spill)
+constexpr int kBatchUnroll = 2;
 
 struct KBatch {
     const KScene* scenes;
@@ -82,7 +85,7 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         wave_sync();
         stage_step_rows(nrows, s_row, s_rb1, s_rsb2, S.t, H, d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
-        step_all_groups<BF16, NOISE>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
+        step_all_groups<BF16, NOISE, kBatchUnroll>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
     }
     wave_sync();   // the next unit reuses this wave's LDS rows
 }

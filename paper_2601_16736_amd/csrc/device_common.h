@@ -487,17 +487,14 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
     }
 }
 
-// Every group's pass over the staged rows.
-#ifndef GS_STEP_UNROLL
-#define GS_STEP_UNROLL 2
-#endif
-
-template <bool BF16, bool NOISE>
+// Every group's pass over the staged rows.  U: (row, chunk) items per lane
+// per trip for the 16/8-byte groups (twice that for 4-byte ones); the noise
+// group, whose items carry the displacement arithmetic, uses 4.
+template <bool BF16, bool NOISE, int U>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
                                                 const int* s_row, const float* s_rb1, const float* s_rsb2,
                                                 int lane)
 {
-    constexpr int U = GS_STEP_UNROLL;
     // With position noise the mean group goes first, so the quaternion,
     // log-scale and opacity rows it reads are still the pre-update ones.
     // Groups are indexed directly (no switch over constant indices): the
@@ -517,7 +514,7 @@ __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H
                                     ? (float)(G.dar_lambda / H.reg_norm)
                                     : (float)G.dar_lambda;
         const uint64_t s2 = BF16 ? d_stream(seed, kTagSrStep + (uint64_t)first, H.iteration) : 0;
-        step_group<BF16, 1, U * 2, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, &nz);
+        step_group<BF16, 1, 4, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, &nz);
     }
     for (int gi = 0; gi < S.n_groups; ++gi) {
         if (gi == first) continue;
