@@ -13,16 +13,21 @@ Layout: before timing, the scene is put in spatial (Morton) order with the
 library's gs_spatial_order + gs_gather_rows, so that a view's visible rows
 form contiguous index runs (--order index keeps the generated order).
 
-One step = visibility + compaction of the view, Re-State rescale (on RSR
-iterations) and the fused Sparse-Adam + DAR pass, all in the HIP library.
-Inputs are resident in HBM before timing starts.  The metric is attribute
-updates per second (visible primitives x 59 per step / wall time of the
-steps).  The JSON line also carries the roofline of the dominant kernel
-(the fused step) measured with HIP events on the launch stream, the FP64
+One step = visibility of the view, Re-State rescale (on RSR iterations) and
+the fused Sparse-Adam + DAR pass, all in the HIP library.  By default the
+three run in one launch (adamw_gs_step_view: each wave culls a window of 128
+primitives and steps its visible rows); --path two_launch times gs_visibility
+(mask + index list) followed by the compacted step instead.  The two-launch
+path always runs first: it is reported as a variant, and its per-step visible
+counts are the fused path's too, since the two end in bit-identical states
+(checked after the runs).  Inputs are resident in HBM before timing starts.
+The metric is attribute updates per second (visible primitives x 59 per step
+/ wall time of the steps).  The JSON line also carries the roofline of the
+dominant kernel measured with HIP events on the launch stream, the FP64
 oracle timed on the host over a bounded sample of the same workload, and the
 other layouts / moment precisions measured the same way ("variants").
 
-Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--path view|two_launch]
        [--order morton|index] [--moments f32|bf16] [--no-variants] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -54,11 +59,13 @@ BYTES_PER_VISIBLE = {"f32": 59 * (4 + 4 + 4 + 4 + 4 + 4 + 4) + 8 + 4,      # 166
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
 N_GRAD_SETS = 4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")
-
-
-# the sources that define the fused step kernel
-STEP_KERNEL_SOURCES = ("internal.h", "device_common.h", "step.hip")
+VIEW_UNIT = 128          # primitives per wave window in the fused view step
+CULL_BYTES = 12          # the fused step's cull reads each primitive's mean once more
+# HBM counter summaries per path, and the sources of the kernel each covers
+TRAFFIC_FILES = {"view": os.path.join(ROOT, "profiles", "step_view_kernel_3M_traffic.json"),
+                 "two_launch": os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")}
+KERNEL_SOURCES = {"view": ("internal.h", "device_common.h", "predicate.h", "step_view.hip"),
+                  "two_launch": ("internal.h", "device_common.h", "step.hip")}
 
 
 class TimingEvents:
@@ -104,23 +111,25 @@ class TimingEvents:
         self.start, self.end = [], []
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(path: str = "view") -> str:
     h = hashlib.sha256()
-    for name in STEP_KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[path]:
         with open(os.path.join(ROOT, "paper_2601_16736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(order: str, moments: str):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source and layout."""
+def measured_traffic(order: str, moments: str, path: str = "view"):
+    """HBM bytes per launch of the path's dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and layout."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[path]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash() or d.get("order") != order or d.get("moments") != moments:
+    if (d.get("source_hash") != kernel_source_hash(path) or d.get("order") != order
+            or d.get("moments") != moments):
         return None
     return d.get("bytes_per_launch")
 
@@ -197,8 +206,14 @@ class SceneOnDevice:
         torch.cuda.synchronize()
 
 
-def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: int, warmup: int):
-    """Times `steps` whole steps (after `warmup`) on fresh optimizer state."""
+def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: int, warmup: int,
+              path: str = "two_launch", counts_from=None, keep_state: bool = False):
+    """Times `steps` whole steps (after `warmup`) on fresh optimizer state.
+    path "two_launch": gs_visibility (mask + index list) then the compacted
+    step; "view": adamw_gs_step_view, visibility fused into the step (one
+    launch, windows of 128).  The fused path writes no count, so its visible
+    counts are taken from a two-launch run on the same cameras (`counts_from`),
+    whose results are bit-identical."""
     import synth
     dev = torch.device("cuda:0")
     mdt = torch.bfloat16 if moments == "bf16" else torch.float32
@@ -233,6 +248,23 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
         if slot >= 0:
             ev.record("end", slot, stream)
 
+    def one_view_step(k: int, slot: int = -1):
+        for G, sets in zip(groups, sd.grads):
+            G.grad = sets[k % N_GRAD_SETS]
+        cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
+                            rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, moment_dtype=mom,
+                            stochastic_round=True, unit=VIEW_UNIT)
+        if slot >= 0:
+            ev.record("start", slot, stream)
+        gs.adamw_gs_step_view(groups, N_PRIMS, t, cfg, means, gcams[order[k]], stream=stream)
+        if slot >= 0:
+            ev.record("end", slot, stream)
+
+    if path == "view":
+        if counts_from is None:
+            raise ValueError("the fused path needs the visible counts of a two-launch run")
+        one_step = one_view_step  # noqa: F811
+
     for k in range(warmup):
         one_step(k)
     torch.cuda.synchronize()
@@ -242,20 +274,26 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    nv = counts.cpu().numpy()[warmup:].astype(np.int64)
+    all_counts = counts.cpu().numpy().astype(np.int64) if path != "view" else np.asarray(counts_from)
+    nv = all_counts[warmup:warmup + steps]
     durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
     ev.close()
     plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
     step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments]
+    if path == "view":
+        step_bytes = step_bytes + N_PRIMS * CULL_BYTES
     achieved = float(step_bytes.sum() / durs[plain].sum()) / 1e9 if plain.any() else float("nan")
+    state = (groups, t) if keep_state else None
     del groups, t, mask, idx
     torch.cuda.empty_cache()
     return {
+        "state": state,
         "value": int(nv.sum()) * 59 / wall,
         "ms_per_step": wall / steps * 1e3,
         "visible_mean": float(nv.mean()),
         "achieved_GBps": achieved,
         "step_kernel_us": float(durs[plain].mean() * 1e6) if plain.any() else float("nan"),
+        "counts": all_counts,
     }
 
 
@@ -430,6 +468,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--order", choices=["morton", "index"], default="morton")
     ap.add_argument("--moments", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--path", choices=["view", "two_launch"], default="view",
+                    help="view: visibility fused into the step (one launch); two_launch: gs_visibility + step")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -463,11 +503,34 @@ def main(argv=None) -> int:
     order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
 
     layouts = {args.order: SceneOnDevice(gs, torch, scene, args.order)}
-    print(f"bench: {args.order} order, {args.moments} moments: {args.steps} steps", file=sys.stderr, flush=True)
-    head = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup)
-
+    # the two-launch path (gs_visibility, then the compacted step) always runs
+    # first: it is a variant line, and its per-step visible counts are the
+    # fused path's too, since both produce the same bits (checked below)
+    print(f"bench: {args.order} order, {args.moments} moments, two launches: {args.steps} steps",
+          file=sys.stderr, flush=True)
+    two = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup,
+                    path="two_launch", keep_state=args.path == "view")
+    two_counts = two.pop("counts")
     variants = []
-    if not args.no_variants:
+    if args.path == "view":
+        print(f"bench: {args.order} order, {args.moments} moments, visibility fused into the step: "
+              f"{args.steps} steps", file=sys.stderr, flush=True)
+        head = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup,
+                         path="view", counts_from=two_counts, keep_state=True)
+        head.pop("counts")
+        (ga, ta), (gb, tb) = two.pop("state"), head.pop("state")
+        same = torch.equal(ta, tb) and all(torch.equal(a.param, b.param) and torch.equal(a.exp_avg, b.exp_avg)
+                                           and torch.equal(a.exp_avg_sq, b.exp_avg_sq) for a, b in zip(ga, gb))
+        del ga, ta, gb, tb
+        torch.cuda.empty_cache()
+        if not same:
+            raise RuntimeError("the fused and two-launch paths ended in different states")
+        two.update({"order": args.order, "moments": args.moments, "path": "two_launch",
+                    "frac": two["achieved_GBps"] / HBM_PEAK_GBS})
+        variants.append(two)
+    else:
+        two.pop("state")
+        head = two
         for o, mo in (("index", "f32"), ("morton", "f32"), ("morton", "bf16"), ("index", "bf16")):
             if (o, mo) == (args.order, args.moments):
                 continue
@@ -475,6 +538,8 @@ def main(argv=None) -> int:
                 layouts[o] = SceneOnDevice(gs, torch, scene, o)
             print(f"bench: variant {o} order, {mo} moments", file=sys.stderr, flush=True)
             r = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup)
+            r.pop("counts")
+            r.pop("state")
             r.update({"order": o, "moments": mo, "frac": r["achieved_GBps"] / HBM_PEAK_GBS})
             variants.append(r)
         del layouts
@@ -499,25 +564,29 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {
             "workload": "3M-primitive scene, 59 FP32 attributes per Gaussian, 200-camera rig (z_far 17.5), "
-                        "visibility + compaction + RSR + fused Sparse-Adam/DAR step",
+                        + ("visibility + RSR + Sparse-Adam/DAR step in one launch" if args.path == "view" else
+                           "visibility + compaction, then RSR + fused Sparse-Adam/DAR step"),
             "n_primitives": N_PRIMS,
             "primitive_order": args.order,
             "moments": args.moments,
             "visible_mean": head["visible_mean"],
             "visible_frac": head["visible_mean"] / N_PRIMS,
-            "schedule": "compacted",
-            "unit_rows": STEP_LAUNCH["unit"],
+            "path": args.path,
+            "schedule": "view windows" if args.path == "view" else "compacted",
+            "unit": VIEW_UNIT if args.path == "view" else STEP_LAUNCH["unit"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "step_kernel (fused Sparse-Adam + DAR)",
+            "kernel": ("step_view_kernel (visibility + Sparse-Adam + DAR, one launch)" if args.path == "view"
+                       else "step_kernel (fused Sparse-Adam + DAR)"),
             "achieved": head["achieved_GBps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["achieved_GBps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.order, args.moments),
+            "traffic": measured_traffic(args.order, args.moments, args.path),
             "step_kernel_us": head["step_kernel_us"],
             "bytes_per_visible": BYTES_PER_VISIBLE[args.moments],
+            "bytes_per_primitive": CULL_BYTES if args.path == "view" else 0,
         },
         "cpu_baseline": None,
         "variants": variants,

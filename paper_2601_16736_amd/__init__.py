@@ -91,6 +91,9 @@ _lib.gs_reg_norm.restype = ctypes.c_double
 _lib.gs_reg_norm.argtypes = [ctypes.c_double]
 _lib.gs_visibility.restype = _i32
 _lib.gs_visibility.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
+_lib.adamw_gs_step_view.restype = _i32
+_lib.adamw_gs_step_view.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, ctypes.POINTER(gs_camera), _vp, _vp,
+                                    ctypes.POINTER(gs_step_config), _vp]
 _lib.gs_visibility_multi.restype = _i32
 _lib.gs_visibility_multi.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.gs_compact.restype = _i32
@@ -131,7 +134,7 @@ _lib.gs_append.restype = _i32
 _lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64, _vp, _vp]
 
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_visibility_multi", "gs_compact",
-            "adamw_gs_step", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
+            "adamw_gs_step", "adamw_gs_step_view", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
             "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
             "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
             "gs_prune", "gs_append"]
@@ -308,6 +311,16 @@ def adamw_gs_step(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, 
     c = cfg.to_c()
     _check(_lib.adamw_gs_step(arr, len(groups), int(n), _ptr(visible), _ptr(vis_idx), _ptr(vis_count),
                               _ptr(step_count), ctypes.byref(c), _stream(stream)))
+
+
+def adamw_gs_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, means, cam: Camera,
+                       radius=None, visible_out=None, stream=None) -> None:
+    """Visibility and step in one launch (see include/gsopt.h)."""
+    arr = _groups_c(groups)
+    c = cfg.to_c()
+    cc = cam.to_c()
+    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _ptr(radius), ctypes.byref(cc),
+                                   _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream)))
 
 
 # --------------------------------------------------------------------------

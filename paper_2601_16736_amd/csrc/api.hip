@@ -378,4 +378,36 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step launch");
 }
 
+gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n, const float* means,
+                             const float* radius, const gs_camera* cam, uint8_t* visible_out, int32_t* step_count,
+                             const gs_step_config* cfg, hipStream_t stream)
+{
+    clear_error();
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    if (cam == nullptr) return fail(GS_EINVAL, "cam is NULL");
+    if (n > 0 && (step_count == nullptr || means == nullptr)) return fail(GS_EINVAL, "step_count or means is NULL");
+    if (!aligned(step_count, 4) || !aligned(means, 4) || !aligned(radius, 4))
+        return fail(GS_EINVAL, "misaligned step_count/means/radius");
+    KCamera k;
+    gs_status st = to_kcamera(cam, &k, "");
+    if (st != GS_OK) return st;
+    KHyper h;
+    st = build_hyper(cfg, any_adaptive(groups, n_groups), &h);
+    if (st != GS_OK) return st;
+    KScene s;
+    memset(&s, 0, sizeof s);
+    st = build_groups(groups, n_groups, n, cfg->moment_dtype, cfg, &s, "");
+    if (st != GS_OK) return st;
+    st = check_noise_groups(cfg, groups, n_groups, "");
+    if (st != GS_OK) return st;
+    const int unit = cfg->unit == 0 ? 128 : cfg->unit;
+    if (unit != 64 && unit != 128 && unit != 256)
+        return fail(GS_EINVAL, "unit = %d: the view step takes 64, 128 or 256 primitives per wave", cfg->unit);
+    s.sched = kSchedMasked;
+    s.unit = unit;
+    s.t = step_count;
+    const hipError_t e = launch_step_view(s, h, k, means, radius, visible_out, stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step_view launch");
+}
+
 }  // extern "C"

@@ -100,6 +100,8 @@ hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t*
 hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream);
 hipError_t launch_invisible(const KScene& s, const KHyper& h, hipStream_t stream);
 size_t step_kernel_units(const KScene& s);
+hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCamera& cam, const float* means,
+                            const float* radius, uint8_t* mask_out, hipStream_t stream);
 
 // batched
 struct BatchDevice;  // defined in batched.hip

@@ -184,6 +184,22 @@ def test_visibility_multi_rejects_bad_arguments():
     assert "view 1" in str(e.value)
 
 
+def test_view_step_rejects_bad_arguments():
+    """Every call here fails validation before any launch."""
+    cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
+    bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000, z_near=5, z_far=5)
+    groups = [_group(param=_Fake(FAKE, (10, 3)))]
+    cases = [dict(n=-1), dict(means=None), dict(t=None), dict(cam=bad), dict(unit=512), dict(unit=32),
+             dict(means=FAKE + 2), dict(beta1=1.0)]
+    for c in cases:
+        n = c.get("n", 10)
+        cfg = gs.StepConfig(unit=c.get("unit", 0), beta1=c.get("beta1", 0.9))
+        with pytest.raises(gs.GsError) as e:
+            gs.adamw_gs_step_view(groups, n, c.get("t", FAKE + 65536), cfg, c.get("means", FAKE + 131072),
+                                  c.get("cam", cam), stream=0)
+        assert e.value.status == gs.GS_EINVAL, c
+
+
 def _prune(n=10, src=None, dst=None, dtype=0, keep=FAKE + 65536, t_src=FAKE + 131072, t_dst=FAKE + 196608,
            cnt=FAKE + 262144, ws=None):
     src = [_group(param=_Fake(FAKE, (n, 3)))] if src is None else src

@@ -1,0 +1,158 @@
+"""The fused view step (visibility and step in one launch) against the
+two-launch path it replaces and against the oracle, through the C ABI.
+
+Rows are independent, so the fused kernel must reproduce gs_visibility
+followed by the masked step bit for bit: attributes, moments, step counts
+and the mask, with Re-State, AIU, position noise and the radius cull on or
+off, in FP32 and BF16, for every wave unit and ragged sizes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+gs = pytest.importorskip("paper_2601_16736_amd")
+from _gpu_util import DEV, compare, make_state, oracle_config, oracle_groups, set_grads  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def _bits(x):
+    return x.view(torch.int16) if x.dtype == torch.bfloat16 else x
+
+
+def _clone(st):
+    return [gs.Group(g.param.clone(), g.grad.clone(), g.exp_avg.clone(), g.exp_avg_sq.clone(), g.lr,
+                     dar_kind=g.dar_kind, dar_lambda=g.dar_lambda, dar_clip=g.dar_clip, reg_mode=g.reg_mode)
+            for g in st.groups], st.t.clone()
+
+
+def _scene(n, seed, bf16):
+    st = make_state(gs, n, synth.GROUPS_59, seed, bf16=bf16)
+    r = synth.rng(seed, 3)
+    st.groups[0].param.copy_(torch.from_numpy(r.uniform(-10, 10, (n, 3)).astype(np.float32)))
+    o = r.uniform(1e-4, 0.9, n)
+    st.groups[3].param.copy_(torch.from_numpy(np.log(o / (1 - o)).astype(np.float32)[:, None]))
+    gr = synth.grads(n, synth.GROUPS_59, np.ones(n, np.uint8), seed, 0)
+    for (name, *_), g in zip(synth.GROUPS_59, st.groups):
+        g.grad.copy_(torch.from_numpy(gr[name]))
+    return st
+
+
+CASES = [  # (n, unit, bf16, rsr, aiu, noise, radius)
+    (1, 128, False, False, False, False, False),
+    (63, 64, True, True, False, False, True),
+    (1025, 128, False, True, True, False, False),
+    (1025, 256, True, True, True, True, True),
+    (20_011, 64, False, False, False, True, False),
+    (20_011, 128, True, True, False, False, False),
+    (20_011, 256, False, True, True, True, True),
+    (100_003, 128, False, True, False, False, False),
+]
+
+
+@pytest.mark.parametrize("n,unit,bf16,rsr,aiu,noise,radius", CASES)
+def test_view_step_equals_visibility_then_step(n, unit, bf16, rsr, aiu, noise, radius):
+    st = _scene(n, 40 + n % 97, bf16)
+    ref_groups, ref_t = _clone(st)
+    rig = synth.camera_rig()
+    c = rig[(n * 7) % 200]
+    rad = torch.from_numpy((synth.rng(n, 9).random(n) * 0.5).astype(np.float32)).to(DEV) if radius else None
+    cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far,
+                    0.5 if radius else 0.0)
+    kw = dict(iteration=17, seed=n, moment_dtype=int(bf16), stochastic_round=bf16, rsr_enable=rsr, rsr_ratio=0.3,
+              aiu_enable=aiu, aiu_ratio=0.4, aiu_scale=0.5, noise_enable=noise, noise_lr=0.02 / 1.6e-4,
+              noise_t=0.5, unit=unit)
+    print(f"view n={n} unit={unit} bf16={bf16} rsr={rsr} aiu={aiu} noise={noise} radius={radius}", flush=True)
+    # reference: the two launches
+    mask_ref = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.gs_visibility(ref_groups[0].param, cam, mask=mask_ref, radius=rad)
+    ref_kw = dict(kw, unit=max(unit, 128))          # the masked schedule's smallest window; rows are independent
+    gs.adamw_gs_step(ref_groups, n, ref_t, gs.StepConfig(schedule=gs.GS_SCHED_MASKED, **ref_kw), visible=mask_ref)
+    # fused
+    mask = torch.full((n,), 9, dtype=torch.uint8, device=DEV)
+    gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(**kw), st.groups[0].param, cam, radius=rad,
+                          visible_out=mask)
+    torch.cuda.synchronize()
+    assert torch.equal(mask, mask_ref)
+    assert torch.equal(st.t, ref_t)
+    for a, b in zip(st.groups, ref_groups):
+        assert torch.equal(a.param, b.param)
+        assert torch.equal(_bits(a.exp_avg), _bits(b.exp_avg))
+        assert torch.equal(_bits(a.exp_avg_sq), _bits(b.exp_avg_sq))
+
+
+def test_view_step_against_oracle():
+    """Mask from the oracle's FP32 predicate, then the oracle step."""
+    n, spec = 30_000, synth.GROUPS_59
+    st = _scene(n, 77, False)
+    c = synth.camera_rig()[123]
+    cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+    cfg = gs.StepConfig(iteration=5, seed=3, rsr_enable=True, rsr_ratio=0.2, reg_norm=1e5)
+    torch.cuda.synchronize()
+    before = st.host()
+    mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.adamw_gs_step_view(st.groups, n, st.t, cfg, st.groups[0].param, cam, visible_out=mask)
+    torch.cuda.synchronize()
+    ocam = oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+    m_ref = oracle.visibility(before["means"]["param"].astype(np.float32), ocam)
+    np.testing.assert_array_equal(mask.cpu().numpy(), m_ref)
+    og = oracle_groups(before, spec, st.groups)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, n, m_ref, t_ref, oracle_config(cfg))
+    touched = m_ref.astype(bool) | oracle.rsr_sample_mask(cfg.seed, cfg.iteration, n, cfg.rsr_ratio)
+    compare(st.host(), before, og, spec, t_ref, touched, False, "view step")
+
+
+def test_view_step_full_size_equals_two_launches():
+    """The benchmark's 3M Morton scene, one step, both paths bit for bit."""
+    import bench
+    scene = synth.scene_uniform(bench.N_PRIMS, seed=0)
+    sd = bench.SceneOnDevice(gs, torch, scene, "morton")
+    n = bench.N_PRIMS
+    cams = synth.camera_rig()
+    c = cams[11]
+    cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+    outs = []
+    for fused in (False, True):
+        groups = [gs.Group(p.clone(), sets[1], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                           dar_lambda=1e-3 if dar == 1 else (1e-5 if dar == 2 else 0.0), dar_clip=10.0)
+                  for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
+        t = torch.zeros(n, dtype=torch.int32, device=DEV)
+        mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        cfg = gs.StepConfig(reg_norm=1e5, iteration=100, rsr_enable=True, rsr_ratio=0.05, unit=128)
+        if fused:
+            gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, cam, visible_out=mask)
+        else:
+            gs.gs_visibility(groups[0].param, cam, mask=mask)
+            cfg.schedule = gs.GS_SCHED_MASKED
+            gs.adamw_gs_step(groups, n, t, cfg, visible=mask)
+        torch.cuda.synchronize()
+        outs.append((groups, t, mask))
+    (ga, ta, ma), (gb, tb, mb) = outs
+    assert torch.equal(ma, mb) and torch.equal(ta, tb)
+    assert 0.2 < ma.float().mean().item() < 0.4
+    for a, b in zip(ga, gb):
+        assert torch.equal(a.param, b.param)
+        assert torch.equal(a.exp_avg, b.exp_avg)
+        assert torch.equal(a.exp_avg_sq, b.exp_avg_sq)
+
+
+def test_view_step_rejects_bad_unit_and_camera():
+    n = 100
+    st = _scene(n, 5, False)
+    c = synth.camera_rig()[0]
+    cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(unit=512), st.groups[0].param, cam)
+    bad = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, 0, c.height, c.z_near, c.z_far)
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, bad)
