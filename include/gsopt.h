@@ -258,21 +258,23 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n,
                         int32_t* step_count, const gs_step_config* cfg, hipStream_t stream);
 
 /*
- * Visibility and step in one launch: the predicate of gs_visibility (camera
- * cam, optional radius) decides V for every primitive from `means` [n][3]
- * as they are when the call starts, then the step above runs with that V.
- * Each wave takes a window of cfg->unit primitives (64, 128 or 256; 0 =
- * 128): it culls the window, steps its visible rows and, when Re-State or
- * AIU is on, treats its invisible sampled rows, so no mask or index list
- * passes through memory in between.  Results equal gs_visibility followed
+ * Visibility and step in one launch: the predicate of gs_visibility
+ * (optional radius) decides V for every primitive from `means` [n][3] as
+ * they are when the call starts, then the step above runs with that V.
+ * With several cameras (n_cams in 1..32, a host array; a batch of training
+ * views) V is their union, as the mask of gs_visibility_multi.  Each wave
+ * takes a window of cfg->unit primitives (64, 128 or 256; 0 = 128): it
+ * culls the window, steps its visible rows and, when Re-State or AIU is
+ * on, treats its invisible sampled rows, so no mask or index list passes
+ * through memory in between.  Results equal the visibility call followed
  * by adamw_gs_step with that mask, bit for bit.  cfg->schedule and
  * cfg->visible_hint are ignored.  means is normally the mean group's param
  * array (any [n][3] FP32 array works); visible_out [n] uint8 receives V, or
  * is NULL.  Other arguments as for adamw_gs_step.
  */
 gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n,
-                             const float* means, const float* radius, const gs_camera* cam,
-                             uint8_t* visible_out, int32_t* step_count,
+                             const float* means, const float* radius, const gs_camera* cams,
+                             int32_t n_cams, uint8_t* visible_out, int32_t* step_count,
                              const gs_step_config* cfg, hipStream_t stream);
 
 /* ------------------------------------------------------------------------

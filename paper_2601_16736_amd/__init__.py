@@ -92,8 +92,8 @@ _lib.gs_reg_norm.argtypes = [ctypes.c_double]
 _lib.gs_visibility.restype = _i32
 _lib.gs_visibility.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
 _lib.adamw_gs_step_view.restype = _i32
-_lib.adamw_gs_step_view.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, ctypes.POINTER(gs_camera), _vp, _vp,
-                                    ctypes.POINTER(gs_step_config), _vp]
+_lib.adamw_gs_step_view.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, ctypes.POINTER(gs_camera), _i32,
+                                    _vp, _vp, ctypes.POINTER(gs_step_config), _vp]
 _lib.gs_visibility_multi.restype = _i32
 _lib.gs_visibility_multi.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.gs_compact.restype = _i32
@@ -313,13 +313,15 @@ def adamw_gs_step(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, 
                               _ptr(step_count), ctypes.byref(c), _stream(stream)))
 
 
-def adamw_gs_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, means, cam: Camera,
+def adamw_gs_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, means, cams,
                        radius=None, visible_out=None, stream=None) -> None:
-    """Visibility and step in one launch (see include/gsopt.h)."""
+    """Visibility and step in one launch (see include/gsopt.h).  ``cams`` is a
+    Camera or a sequence of up to 32 (their union decides V)."""
+    cams = [cams] if isinstance(cams, Camera) else list(cams)
     arr = _groups_c(groups)
     c = cfg.to_c()
-    cc = cam.to_c()
-    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _ptr(radius), ctypes.byref(cc),
+    cc = (gs_camera * max(len(cams), 1))(*[x.to_c() for x in cams])
+    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _ptr(radius), cc, len(cams),
                                    _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream)))
 
 

@@ -379,18 +379,26 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
 }
 
 gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n, const float* means,
-                             const float* radius, const gs_camera* cam, uint8_t* visible_out, int32_t* step_count,
-                             const gs_step_config* cfg, hipStream_t stream)
+                             const float* radius, const gs_camera* cams, int32_t n_cams, uint8_t* visible_out,
+                             int32_t* step_count, const gs_step_config* cfg, hipStream_t stream)
 {
     clear_error();
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
-    if (cam == nullptr) return fail(GS_EINVAL, "cam is NULL");
+    if (cams == nullptr) return fail(GS_EINVAL, "cams is NULL");
+    if (n_cams < 1 || n_cams > kMaxViews) return fail(GS_EINVAL, "n_cams = %d, must be in [1, %d]", n_cams, kMaxViews);
     if (n > 0 && (step_count == nullptr || means == nullptr)) return fail(GS_EINVAL, "step_count or means is NULL");
     if (!aligned(step_count, 4) || !aligned(means, 4) || !aligned(radius, 4))
         return fail(GS_EINVAL, "misaligned step_count/means/radius");
-    KCamera k;
-    gs_status st = to_kcamera(cam, &k, "");
+    KCameras k;
+    memset(&k, 0, sizeof k);
+    gs_status st = GS_OK;
+    for (int v = 0; v < n_cams && st == GS_OK; ++v) {
+        char prefix[32];
+        snprintf(prefix, sizeof prefix, n_cams > 1 ? "view %d: " : "", v);
+        st = to_kcamera(&cams[v], &k.c[v], prefix);
+    }
     if (st != GS_OK) return st;
+    k.n = n_cams;
     KHyper h;
     st = build_hyper(cfg, any_adaptive(groups, n_groups), &h);
     if (st != GS_OK) return st;

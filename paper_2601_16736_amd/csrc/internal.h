@@ -93,6 +93,8 @@ uint64_t splitmix_output(uint64_t s, uint64_t k);
 
 hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
                              uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream);
+hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means,
+                            const float* radius, uint8_t* mask_out, hipStream_t stream);
 hipError_t launch_visibility_multi(const float* means, const float* radius, int64_t n, const KCameras& cams,
                                    uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count, hipStream_t stream);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream);
@@ -100,8 +102,7 @@ hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t*
 hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream);
 hipError_t launch_invisible(const KScene& s, const KHyper& h, hipStream_t stream);
 size_t step_kernel_units(const KScene& s);
-hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCamera& cam, const float* means,
-                            const float* radius, uint8_t* mask_out, hipStream_t stream);
+
 
 // batched
 struct BatchDevice;  // defined in batched.hip

@@ -16,8 +16,21 @@ namespace gs {
 #define GS_STEP_UNROLL_BF16 2
 #endif
 
-template <bool BF16, int UNIT, bool NOISE, bool RADIUS>
-__global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, KCamera cam,
+// Visible from the one camera, or (CAMS = KCameras) from any camera of the batch.
+__device__ __forceinline__ bool visible_any(float x, float y, float z, const float* rho, const KCamera& c)
+{
+    return visible_pred(x, y, z, rho, c);
+}
+
+__device__ __forceinline__ bool visible_any(float x, float y, float z, const float* rho, const KCameras& cs)
+{
+    bool v = false;
+    for (int k = 0; k < cs.n; ++k) v = v || visible_pred(x, y, z, rho, cs.c[k]);
+    return v;
+}
+
+template <bool BF16, int UNIT, bool NOISE, bool RADIUS, typename CAMS>
+__global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, CAMS cam,
                                                            const float* __restrict__ means,
                                                            const float* __restrict__ radius,
                                                            uint8_t* __restrict__ mask_out)
@@ -45,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, K
 #pragma unroll
     for (int b = 0; b < R; ++b) {
         in[b] = w0 + b * kWave + lane < S.n;
-        vis[b] = in[b] && visible_pred(x[b], y[b], z[b], RADIUS ? &rho[b] : nullptr, cam);
+        vis[b] = in[b] && visible_any(x[b], y[b], z[b], RADIUS ? &rho[b] : nullptr, cam);
         if (mask_out != nullptr && in[b]) mask_out[w0 + b * kWave + lane] = (uint8_t)vis[b];
     }
 
@@ -103,39 +116,52 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, K
 
 namespace {
 
-using ViewFn = void (*)(KScene, KHyper, KCamera, const float*, const float*, uint8_t*);
+template <typename CAMS>
+using ViewFn = void (*)(KScene, KHyper, CAMS, const float*, const float*, uint8_t*);
 
-template <bool BF16, bool NOISE, bool RADIUS>
-ViewFn pick_view(int unit)
+template <bool BF16, bool NOISE, bool RADIUS, typename CAMS>
+ViewFn<CAMS> pick_view(int unit)
 {
     switch (unit) {
-    case 64: return step_view_kernel<BF16, 64, NOISE, RADIUS>;
-    case 128: return step_view_kernel<BF16, 128, NOISE, RADIUS>;
-    case 256: return step_view_kernel<BF16, 256, NOISE, RADIUS>;
+    case 64: return step_view_kernel<BF16, 64, NOISE, RADIUS, CAMS>;
+    case 128: return step_view_kernel<BF16, 128, NOISE, RADIUS, CAMS>;
+    case 256: return step_view_kernel<BF16, 256, NOISE, RADIUS, CAMS>;
     default: return nullptr;
     }
 }
 
-template <bool BF16>
-ViewFn pick_view(int unit, bool noise, bool radius)
+template <typename CAMS>
+ViewFn<CAMS> pick_view(bool bf16, int unit, bool noise, bool radius)
 {
-    if (noise) return radius ? pick_view<BF16, true, true>(unit) : pick_view<BF16, true, false>(unit);
-    return radius ? pick_view<BF16, false, true>(unit) : pick_view<BF16, false, false>(unit);
+    if (bf16) {
+        if (noise) return radius ? pick_view<true, true, true, CAMS>(unit) : pick_view<true, true, false, CAMS>(unit);
+        return radius ? pick_view<true, false, true, CAMS>(unit) : pick_view<true, false, false, CAMS>(unit);
+    }
+    if (noise) return radius ? pick_view<false, true, true, CAMS>(unit) : pick_view<false, true, false, CAMS>(unit);
+    return radius ? pick_view<false, false, true, CAMS>(unit) : pick_view<false, false, false, CAMS>(unit);
+}
+
+template <typename CAMS>
+hipError_t launch_view(const KScene& s, const KHyper& h, const CAMS& cams, const float* means, const float* radius,
+                       uint8_t* mask_out, hipStream_t stream)
+{
+    if (s.n == 0) return hipSuccess;
+    ViewFn<CAMS> fn = pick_view<CAMS>(s.bf16 != 0, s.unit, h.noise != 0, radius != nullptr);
+    if (fn == nullptr) return hipErrorInvalidValue;
+    const int64_t units = (s.n + s.unit - 1) / s.unit;
+    const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, s, h, cams, means, radius, mask_out);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCamera& cam, const float* means,
+// One camera: the camera itself is the kernel argument; several: the batch.
+hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means,
                             const float* radius, uint8_t* mask_out, hipStream_t stream)
 {
-    if (s.n == 0) return hipSuccess;
-    const bool noise = h.noise != 0, rad = radius != nullptr;
-    ViewFn fn = s.bf16 ? pick_view<true>(s.unit, noise, rad) : pick_view<false>(s.unit, noise, rad);
-    if (fn == nullptr) return hipErrorInvalidValue;
-    const int64_t units = (s.n + s.unit - 1) / s.unit;
-    const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, s, h, cam, means, radius, mask_out);
-    return hipGetLastError();
+    if (cams.n == 1) return launch_view(s, h, cams.c[0], means, radius, mask_out, stream);
+    return launch_view(s, h, cams, means, radius, mask_out, stream);
 }
 
 }  // namespace gs

@@ -190,7 +190,7 @@ def test_view_step_rejects_bad_arguments():
     bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000, z_near=5, z_far=5)
     groups = [_group(param=_Fake(FAKE, (10, 3)))]
     cases = [dict(n=-1), dict(means=None), dict(t=None), dict(cam=bad), dict(unit=512), dict(unit=32),
-             dict(means=FAKE + 2), dict(beta1=1.0)]
+             dict(means=FAKE + 2), dict(beta1=1.0), dict(cam=[]), dict(cam=[cam] * 33), dict(cam=[cam, bad])]
     for c in cases:
         n = c.get("n", 10)
         cfg = gs.StepConfig(unit=c.get("unit", 0), beta1=c.get("beta1", 0.9))

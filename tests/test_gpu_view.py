@@ -4,7 +4,8 @@ two-launch path it replaces and against the oracle, through the C ABI.
 Rows are independent, so the fused kernel must reproduce gs_visibility
 followed by the masked step bit for bit: attributes, moments, step counts
 and the mask, with Re-State, AIU, position noise and the radius cull on or
-off, in FP32 and BF16, for every wave unit and ragged sizes."""
+off, in FP32 and BF16, for every wave unit and ragged sizes; with a batch
+of cameras, the union of their views decides V."""
 import numpy as np
 import pytest
 import torch
@@ -90,6 +91,33 @@ def test_view_step_equals_visibility_then_step(n, unit, bf16, rsr, aiu, noise, r
         assert torch.equal(_bits(a.exp_avg_sq), _bits(b.exp_avg_sq))
 
 
+@pytest.mark.parametrize("views,unit,bf16,rsr", [(2, 128, False, True), (5, 64, True, False), (32, 256, False, True)])
+def test_view_step_camera_batch_equals_union_then_step(views, unit, bf16, rsr):
+    """Several cameras: V is their union, as gs_visibility_multi's mask."""
+    n = 40_009
+    st = _scene(n, 90 + views, bf16)
+    ref_groups, ref_t = _clone(st)
+    rig = synth.camera_rig()
+    cams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+            for c in (rig[(11 * v + views) % 200] for v in range(views))]
+    kw = dict(iteration=3, seed=views, moment_dtype=int(bf16), stochastic_round=bf16, rsr_enable=rsr, rsr_ratio=0.2,
+              unit=unit)
+    mask_ref = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.gs_visibility_multi(ref_groups[0].param, cams, mask=mask_ref)
+    gs.adamw_gs_step(ref_groups, n, ref_t, gs.StepConfig(schedule=gs.GS_SCHED_MASKED, **dict(kw, unit=max(unit, 128))),
+                     visible=mask_ref)
+    mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(**kw), st.groups[0].param, cams, visible_out=mask)
+    torch.cuda.synchronize()
+    assert torch.equal(mask, mask_ref)
+    assert mask.float().mean().item() > 0.3          # the union of several views
+    assert torch.equal(st.t, ref_t)
+    for a, b in zip(st.groups, ref_groups):
+        assert torch.equal(a.param, b.param)
+        assert torch.equal(_bits(a.exp_avg), _bits(b.exp_avg))
+        assert torch.equal(_bits(a.exp_avg_sq), _bits(b.exp_avg_sq))
+
+
 def test_view_step_against_oracle():
     """Mask from the oracle's FP32 predicate, then the oracle step."""
     n, spec = 30_000, synth.GROUPS_59
@@ -156,3 +184,9 @@ def test_view_step_rejects_bad_unit_and_camera():
     bad = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, 0, c.height, c.z_near, c.z_far)
     with pytest.raises(gs.GsError):
         gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, bad)
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, [cam, bad])
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, [cam] * 33)
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, [])
