@@ -15,7 +15,7 @@ form contiguous index runs (--order index keeps the generated order).
 
 One step = visibility of the view, Re-State rescale (on RSR iterations) and
 the fused Sparse-Adam + DAR pass, all in the HIP library.  By default the
-three run in one launch (adamw_gs_step_view: each wave culls a window of 128
+three run in one launch (adamw_gs_step_view: each wave culls a window of 32
 primitives and steps its visible rows); --path two_launch times gs_visibility
 (mask + index list) followed by the compacted step instead.  The two-launch
 path always runs first: it is reported as a variant, and its per-step visible
@@ -59,7 +59,7 @@ BYTES_PER_VISIBLE = {"f32": 59 * (4 + 4 + 4 + 4 + 4 + 4 + 4) + 8 + 4,      # 166
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
 N_GRAD_SETS = 4
-VIEW_UNIT = 128          # primitives per wave window in the fused view step
+VIEW_UNIT = 32           # primitives per wave window in the fused view step
 CULL_BYTES = 12          # the fused step's cull reads each primitive's mean once more
 # HBM counter summaries per path, and the sources of the kernel each covers
 TRAFFIC_FILES = {"view": os.path.join(ROOT, "profiles", "step_view_kernel_3M_traffic.json"),
@@ -211,7 +211,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     """Times `steps` whole steps (after `warmup`) on fresh optimizer state.
     path "two_launch": gs_visibility (mask + index list) then the compacted
     step; "view": adamw_gs_step_view, visibility fused into the step (one
-    launch, windows of 128).  The fused path writes no count, so its visible
+    launch, windows of VIEW_UNIT primitives).  The fused path writes no count, so its visible
     counts are taken from a two-launch run on the same cameras (`counts_from`),
     whose results are bit-identical."""
     import synth

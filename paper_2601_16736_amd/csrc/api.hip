@@ -408,9 +408,9 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     if (st != GS_OK) return st;
     st = check_noise_groups(cfg, groups, n_groups, "");
     if (st != GS_OK) return st;
-    const int unit = cfg->unit == 0 ? 128 : cfg->unit;
-    if (unit != 64 && unit != 128 && unit != 256)
-        return fail(GS_EINVAL, "unit = %d: the view step takes 64, 128 or 256 primitives per wave", cfg->unit);
+    const int unit = cfg->unit == 0 ? 32 : cfg->unit;       // 32: the fastest window on the 3M scene
+    if (unit != 32 && unit != 64 && unit != 128 && unit != 256)
+        return fail(GS_EINVAL, "unit = %d: the view step takes 32, 64, 128 or 256 primitives per wave", cfg->unit);
     s.sched = kSchedMasked;
     s.unit = unit;
     s.t = step_count;

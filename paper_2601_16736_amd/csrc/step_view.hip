@@ -35,7 +35,9 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
                                                            const float* __restrict__ radius,
                                                            uint8_t* __restrict__ mask_out)
 {
-    constexpr int R = UNIT / kWave;
+    // rounds of 64 primitives per lane group; a 32-primitive window leaves the
+    // upper half of the lanes idle during the cull
+    constexpr int R = (UNIT + kWave - 1) / kWave;
     __shared__ int s_row[kWavesPerBlock][UNIT];
     __shared__ float s_rb1[kWavesPerBlock][UNIT];
     __shared__ float s_rsb2[kWavesPerBlock][UNIT];
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
     bool vis[R], in[R];
 #pragma unroll
     for (int b = 0; b < R; ++b) {
-        in[b] = w0 + b * kWave + lane < S.n;
+        in[b] = b * kWave + lane < UNIT && w0 + b * kWave + lane < S.n;
         vis[b] = in[b] && visible_any(x[b], y[b], z[b], RADIUS ? &rho[b] : nullptr, cam);
         if (mask_out != nullptr && in[b]) mask_out[w0 + b * kWave + lane] = (uint8_t)vis[b];
     }
@@ -123,6 +125,7 @@ template <bool BF16, bool NOISE, bool RADIUS, typename CAMS>
 ViewFn<CAMS> pick_view(int unit)
 {
     switch (unit) {
+    case 32: return step_view_kernel<BF16, 32, NOISE, RADIUS, CAMS>;
     case 64: return step_view_kernel<BF16, 64, NOISE, RADIUS, CAMS>;
     case 128: return step_view_kernel<BF16, 128, NOISE, RADIUS, CAMS>;
     case 256: return step_view_kernel<BF16, 256, NOISE, RADIUS, CAMS>;

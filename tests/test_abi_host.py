@@ -14,6 +14,16 @@ HEADER = os.path.join(ROOT, "include", "gsopt.h")
 
 gs = pytest.importorskip("paper_2601_16736_amd", reason="libgsopt.so not built")
 
+# These calls pass fake device addresses and rely on validation failing
+# before any launch.  Where a GPU is present a call that validation let
+# through would launch on them, so the module runs only on GPU-less hosts
+# (counting devices does not initialise the runtime).
+import torch  # noqa: E402
+
+if torch.cuda.device_count() > 0:
+    pytest.skip("host-side ABI checks use fake device pointers; run them where no GPU is present",
+                allow_module_level=True)
+
 FAKE = 0x7F0000000000          # an aligned address that is never dereferenced
 
 
@@ -189,7 +199,7 @@ def test_view_step_rejects_bad_arguments():
     cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
     bad = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000, z_near=5, z_far=5)
     groups = [_group(param=_Fake(FAKE, (10, 3)))]
-    cases = [dict(n=-1), dict(means=None), dict(t=None), dict(cam=bad), dict(unit=512), dict(unit=32),
+    cases = [dict(n=-1), dict(means=None), dict(t=None), dict(cam=bad), dict(unit=512), dict(unit=16),
              dict(means=FAKE + 2), dict(beta1=1.0), dict(cam=[]), dict(cam=[cam] * 33), dict(cam=[cam, bad])]
     for c in cases:
         n = c.get("n", 10)

@@ -50,6 +50,9 @@ def _scene(n, seed, bf16):
 
 CASES = [  # (n, unit, bf16, rsr, aiu, noise, radius)
     (1, 128, False, False, False, False, False),
+    (31, 32, False, True, True, False, True),
+    (20_011, 32, True, True, True, True, False),
+    (100_003, 32, False, True, False, True, True),
     (63, 64, True, True, False, False, True),
     (1025, 128, False, True, True, False, False),
     (1025, 256, True, True, True, True, True),
@@ -91,7 +94,8 @@ def test_view_step_equals_visibility_then_step(n, unit, bf16, rsr, aiu, noise, r
         assert torch.equal(_bits(a.exp_avg_sq), _bits(b.exp_avg_sq))
 
 
-@pytest.mark.parametrize("views,unit,bf16,rsr", [(2, 128, False, True), (5, 64, True, False), (32, 256, False, True)])
+@pytest.mark.parametrize("views,unit,bf16,rsr", [(2, 128, False, True), (5, 64, True, False), (32, 256, False, True),
+                                                 (3, 32, False, True)])
 def test_view_step_camera_batch_equals_union_then_step(views, unit, bf16, rsr):
     """Several cameras: V is their union, as gs_visibility_multi's mask."""
     n = 40_009
@@ -156,12 +160,12 @@ def test_view_step_full_size_equals_two_launches():
                   for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
         t = torch.zeros(n, dtype=torch.int32, device=DEV)
         mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
-        cfg = gs.StepConfig(reg_norm=1e5, iteration=100, rsr_enable=True, rsr_ratio=0.05, unit=128)
+        cfg = gs.StepConfig(reg_norm=1e5, iteration=100, rsr_enable=True, rsr_ratio=0.05, unit=bench.VIEW_UNIT)
         if fused:
             gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, cam, visible_out=mask)
         else:
             gs.gs_visibility(groups[0].param, cam, mask=mask)
-            cfg.schedule = gs.GS_SCHED_MASKED
+            cfg.schedule, cfg.unit = gs.GS_SCHED_MASKED, 128       # the masked schedule's smallest window
             gs.adamw_gs_step(groups, n, t, cfg, visible=mask)
         torch.cuda.synchronize()
         outs.append((groups, t, mask))
@@ -181,6 +185,8 @@ def test_view_step_rejects_bad_unit_and_camera():
     cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
     with pytest.raises(gs.GsError):
         gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(unit=512), st.groups[0].param, cam)
+    with pytest.raises(gs.GsError):
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(unit=16), st.groups[0].param, cam)
     bad = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, 0, c.height, c.z_near, c.z_far)
     with pytest.raises(gs.GsError):
         gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, bad)
