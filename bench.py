@@ -297,6 +297,16 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     }
 
 
+def same_state(torch, a, b) -> bool:
+    """Bit equality of two (groups, step counts) end states."""
+    (ga, ta), (gb, tb) = a, b
+    def bits(x):
+        return x.view(torch.int16) if x.dtype == torch.bfloat16 else x
+    return torch.equal(ta, tb) and all(
+        torch.equal(x.param, y.param) and torch.equal(bits(x.exp_avg), bits(y.exp_avg))
+        and torch.equal(bits(x.exp_avg_sq), bits(y.exp_avg_sq)) for x, y in zip(ga, gb))
+
+
 def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8):
     """Many-scene workload: 16 scenes with sizes log-uniform in [2e5, 4e6] and
     visible ratios U[0.02, 0.60] (Bernoulli visibility, 8 pre-drawn masks per
@@ -518,10 +528,7 @@ def main(argv=None) -> int:
         head = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup,
                          path="view", counts_from=two_counts, keep_state=True)
         head.pop("counts")
-        (ga, ta), (gb, tb) = two.pop("state"), head.pop("state")
-        same = torch.equal(ta, tb) and all(torch.equal(a.param, b.param) and torch.equal(a.exp_avg, b.exp_avg)
-                                           and torch.equal(a.exp_avg_sq, b.exp_avg_sq) for a, b in zip(ga, gb))
-        del ga, ta, gb, tb
+        same = same_state(torch, two.pop("state"), head.pop("state"))
         torch.cuda.empty_cache()
         if not same:
             raise RuntimeError("the fused and two-launch paths ended in different states")
@@ -537,10 +544,23 @@ def main(argv=None) -> int:
             if o not in layouts:
                 layouts[o] = SceneOnDevice(gs, torch, scene, o)
             print(f"bench: variant {o} order, {mo} moments", file=sys.stderr, flush=True)
-            r = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup)
-            r.pop("counts")
-            r.pop("state")
-            r.update({"order": o, "moments": mo, "frac": r["achieved_GBps"] / HBM_PEAK_GBS})
+            fused_too = o == "morton"
+            r = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup, keep_state=fused_too)
+            counts = r.pop("counts")
+            r.update({"order": o, "moments": mo, "path": "two_launch", "frac": r["achieved_GBps"] / HBM_PEAK_GBS})
+            if fused_too:
+                print(f"bench: variant {o} order, {mo} moments, visibility fused into the step",
+                      file=sys.stderr, flush=True)
+                f = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup, path="view",
+                              counts_from=counts, keep_state=True)
+                f.pop("counts")
+                if not same_state(torch, r.pop("state"), f.pop("state")):
+                    raise RuntimeError(f"{o}/{mo}: the fused and two-launch paths ended in different states")
+                torch.cuda.empty_cache()
+                f.update({"order": o, "moments": mo, "path": "view", "frac": f["achieved_GBps"] / HBM_PEAK_GBS})
+                variants.append(f)
+            else:
+                r.pop("state")
             variants.append(r)
         del layouts
         torch.cuda.empty_cache()

@@ -199,7 +199,7 @@ bool any_adaptive(const gs_group* groups, int32_t n_groups)
 
 bool valid_unit(int sched, int unit)
 {
-    if (sched == kSchedCompacted) return unit == 64 || unit == 128 || unit == 256 || unit == 512;
+    if (sched == kSchedCompacted) return unit == 32 || unit == 64 || unit == 128 || unit == 256 || unit == 512;
     if (sched == kSchedMasked) return unit == 128 || unit == 256 || unit == 512;
     if (sched == kSchedDense) return unit == 256 || unit == 512;
     return false;

@@ -66,6 +66,7 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         const int cnt = (int)min((int64_t)*S.count, S.n);
         const int64_t base = local * S.unit;
         switch (S.unit) {
+        case 32: nrows = build_rows_slice<32>(S.idx, cnt, S.n, base, s_row, lane); break;
         case 64: nrows = build_rows_slice<64>(S.idx, cnt, S.n, base, s_row, lane); break;
         case 128: nrows = build_rows_slice<128>(S.idx, cnt, S.n, base, s_row, lane); break;
         case 256: nrows = build_rows_slice<256>(S.idx, cnt, S.n, base, s_row, lane); break;

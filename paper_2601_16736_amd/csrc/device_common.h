@@ -450,16 +450,18 @@ template <int UNIT>
 __device__ __forceinline__ int build_rows_slice(const int32_t* idx, int cnt, int64_t n, int64_t base, int* s_row,
                                                 int lane)
 {
+    // a 32-entry slice leaves the upper half-wave idle (avail <= UNIT)
+    constexpr int R = (UNIT + kWave - 1) / kWave;
     const int avail = (int)min((int64_t)UNIT, (int64_t)cnt - base);
-    int32_t v[UNIT / kWave];
+    int32_t v[R];
 #pragma unroll
-    for (int b = 0; b < UNIT / kWave; ++b) {
+    for (int b = 0; b < R; ++b) {
         const int j = b * kWave + lane;
         v[b] = j < avail ? idx[base + j] : -1;
     }
     int nrows = 0;
 #pragma unroll
-    for (int b = 0; b < UNIT / kWave; ++b) {
+    for (int b = 0; b < R; ++b) {
         const bool ok = v[b] >= 0 && v[b] < n;
         const uint64_t bal = __ballot(ok);
         if (ok) s_row[nrows + lanes_below(bal)] = v[b];

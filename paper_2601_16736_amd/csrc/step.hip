@@ -84,6 +84,7 @@ StepFn pick(int sched, int unit)
 {
     if (sched == kSchedCompacted) {
         switch (unit) {
+        case 32: return step_kernel<BF16, kSchedCompacted, 32, NOISE>;
         case 64: return step_kernel<BF16, kSchedCompacted, 64, NOISE>;
         case 128: return step_kernel<BF16, kSchedCompacted, 128, NOISE>;
         case 256: return step_kernel<BF16, kSchedCompacted, 256, NOISE>;

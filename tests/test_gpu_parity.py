@@ -168,7 +168,7 @@ def test_compact_matches_nonzero(p, n):
 
 
 # ---------------------------------------------------------------- one step
-SCHEDS = [(gs.GS_SCHED_COMPACTED, u) for u in (64, 128, 256, 512)] + \
+SCHEDS = [(gs.GS_SCHED_COMPACTED, u) for u in (32, 64, 128, 256, 512)] + \
          [(gs.GS_SCHED_MASKED, u) for u in (128, 256, 512)] + [(gs.GS_SCHED_DENSE, u) for u in (256, 512)]
 LAYOUTS = {"59": synth.GROUPS_59, "60split": synth.GROUPS_60_SPLIT}
 MOMENTS = {"f32": (False, False), "bf16_rne": (True, False), "bf16_sr": (True, True)}
@@ -216,7 +216,8 @@ def test_step_parity_small(sched, unit, layout, moments, rsr):
 
 @pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65])
 def test_step_tiny_sizes(n):
-    for sched, unit in ((gs.GS_SCHED_COMPACTED, 64), (gs.GS_SCHED_MASKED, 128), (gs.GS_SCHED_DENSE, 256)):
+    for sched, unit in ((gs.GS_SCHED_COMPACTED, 32), (gs.GS_SCHED_COMPACTED, 64), (gs.GS_SCHED_MASKED, 128),
+                        (gs.GS_SCHED_DENSE, 256)):
         _one_step(n, synth.GROUPS_59, sched, unit, False, False, True, seed=3 + n, p_vis=0.5)
 
 
@@ -293,7 +294,7 @@ def test_dense_schedule_is_synchronous_adam():
 def test_auto_schedule_and_tuner():
     n = 50_000
     s, u = gs.gs_tune(n, [d for _, d, _, _ in synth.GROUPS_59], 0.3)
-    assert s in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED) and u in (64, 128, 256, 512)
+    assert s in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED) and u in (32, 64, 128, 256, 512)
     st = make_state(gs, n, synth.GROUPS_59, 8)
     mask = synth.bernoulli_mask(n, 0.3, 8, 1)
     set_grads(st, mask, 8, 1)
