@@ -17,7 +17,8 @@ One step = visibility of the view, Re-State rescale (on RSR iterations) and
 the fused Sparse-Adam + DAR pass, all in the HIP library.  By default the
 three run in one launch (adamw_gs_step_view: each wave culls a window of 32
 primitives and steps its visible rows); --path two_launch times gs_visibility
-(mask + index list) followed by the compacted step instead.  The two-launch
+(mask, index list and count) followed by the masked step (windows of 32)
+instead.  The two-launch
 path always runs first: it is reported as a variant, and its per-step visible
 counts are the fused path's too, since the two end in bit-identical states
 (checked after the runs).  Inputs are resident in HBM before timing starts.
@@ -48,19 +49,21 @@ import numpy as np  # noqa: E402
 
 # Launch configuration of the fused step in the benchmark (the full-size
 # parity test runs the same one).
-STEP_LAUNCH = {"schedule": 1, "unit": 64}           # compacted schedule, 64 rows per wave
+STEP_LAUNCH = {"schedule": 2, "unit": 32}           # masked schedule, windows of 32 primitives
 
 N_PRIMS = 3_000_000
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per visible primitive of the step kernel: theta r/w, g r,
-# m r/w, v r/w over 59 elements; t r/w; its visible-index read
-BYTES_PER_VISIBLE = {"f32": 59 * (4 + 4 + 4 + 4 + 4 + 4 + 4) + 8 + 4,      # 1664
-                     "bf16": 59 * (4 + 4 + 4 + 2 + 2 + 2 + 2) + 8 + 4}     # 1192
+# algorithmic bytes per visible primitive of the step: theta r/w, g r, m r/w,
+# v r/w over 59 elements; t r/w
+BYTES_PER_VISIBLE = {"f32": 59 * (4 + 4 + 4 + 4 + 4 + 4 + 4) + 8,          # 1660
+                     "bf16": 59 * (4 + 4 + 4 + 2 + 2 + 2 + 2) + 8}         # 1188
+# and per primitive of the scene: the masked step reads its mask byte; the
+# fused view step reads its mean once more for the cull
+BYTES_PER_PRIMITIVE = {"two_launch": 1, "view": 12}
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
 N_GRAD_SETS = 4
 VIEW_UNIT = 32           # primitives per wave window in the fused view step
-CULL_BYTES = 12          # the fused step's cull reads each primitive's mean once more
 # HBM counter summaries per path, and the sources of the kernel each covers
 TRAFFIC_FILES = {"view": os.path.join(ROOT, "profiles", "step_view_kernel_3M_traffic.json"),
                  "two_launch": os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")}
@@ -209,8 +212,8 @@ class SceneOnDevice:
 def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: int, warmup: int,
               path: str = "two_launch", counts_from=None, keep_state: bool = False):
     """Times `steps` whole steps (after `warmup`) on fresh optimizer state.
-    path "two_launch": gs_visibility (mask + index list) then the compacted
-    step; "view": adamw_gs_step_view, visibility fused into the step (one
+    path "two_launch": gs_visibility (mask, index list and count) then the
+    masked step; "view": adamw_gs_step_view, visibility fused into the step (one
     launch, windows of VIEW_UNIT primitives).  The fused path writes no count, so its visible
     counts are taken from a two-launch run on the same cameras (`counts_from`),
     whose results are bit-identical."""
@@ -279,9 +282,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
     ev.close()
     plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
-    step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments]
-    if path == "view":
-        step_bytes = step_bytes + N_PRIMS * CULL_BYTES
+    step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments] + N_PRIMS * BYTES_PER_PRIMITIVE[path]
     achieved = float(step_bytes.sum() / durs[plain].sum()) / 1e9 if plain.any() else float("nan")
     state = (groups, t) if keep_state else None
     del groups, t, mask, idx
@@ -513,7 +514,7 @@ def main(argv=None) -> int:
     order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
 
     layouts = {args.order: SceneOnDevice(gs, torch, scene, args.order)}
-    # the two-launch path (gs_visibility, then the compacted step) always runs
+    # the two-launch path (gs_visibility, then the masked step) always runs
     # first: it is a variant line, and its per-step visible counts are the
     # fused path's too, since both produce the same bits (checked below)
     print(f"bench: {args.order} order, {args.moments} moments, two launches: {args.steps} steps",
@@ -538,6 +539,7 @@ def main(argv=None) -> int:
     else:
         two.pop("state")
         head = two
+    if not args.no_variants:
         for o, mo in (("index", "f32"), ("morton", "f32"), ("morton", "bf16"), ("index", "bf16")):
             if (o, mo) == (args.order, args.moments):
                 continue
@@ -585,14 +587,14 @@ def main(argv=None) -> int:
         "config": {
             "workload": "3M-primitive scene, 59 FP32 attributes per Gaussian, 200-camera rig (z_far 17.5), "
                         + ("visibility + RSR + Sparse-Adam/DAR step in one launch" if args.path == "view" else
-                           "visibility + compaction, then RSR + fused Sparse-Adam/DAR step"),
+                           "visibility (mask + compaction), then RSR + fused Sparse-Adam/DAR step"),
             "n_primitives": N_PRIMS,
             "primitive_order": args.order,
             "moments": args.moments,
             "visible_mean": head["visible_mean"],
             "visible_frac": head["visible_mean"] / N_PRIMS,
             "path": args.path,
-            "schedule": "view windows" if args.path == "view" else "compacted",
+            "schedule": "view windows" if args.path == "view" else "masked windows",
             "unit": VIEW_UNIT if args.path == "view" else STEP_LAUNCH["unit"],
         },
         "roofline": {
@@ -606,7 +608,7 @@ def main(argv=None) -> int:
             "traffic": measured_traffic(args.order, args.moments, args.path),
             "step_kernel_us": head["step_kernel_us"],
             "bytes_per_visible": BYTES_PER_VISIBLE[args.moments],
-            "bytes_per_primitive": CULL_BYTES if args.path == "view" else 0,
+            "bytes_per_primitive": BYTES_PER_PRIMITIVE[args.path],
         },
         "cpu_baseline": None,
         "variants": variants,

@@ -200,12 +200,13 @@ bool any_adaptive(const gs_group* groups, int32_t n_groups)
 bool valid_unit(int sched, int unit)
 {
     if (sched == kSchedCompacted) return unit == 32 || unit == 64 || unit == 128 || unit == 256 || unit == 512;
-    if (sched == kSchedMasked) return unit == 128 || unit == 256 || unit == 512;
-    if (sched == kSchedDense) return unit == 256 || unit == 512;
+    if (sched == kSchedMasked) return unit == 32 || unit == 64 || unit == 128 || unit == 256 || unit == 512;
+    if (sched == kSchedDense) return unit == 64 || unit == 256 || unit == 512;
     return false;
 }
 
-int default_unit(int sched) { return sched == kSchedCompacted ? 128 : 512; }
+// Units that were fastest on the 3M-primitive scene (Morton order, 29 % visible).
+int default_unit(int sched) { return sched == kSchedCompacted ? 64 : sched == kSchedMasked ? 32 : 64; }
 
 // Resolves the schedule and unit of a scene from what the caller supplied.
 gs_status resolve_schedule(int requested, int unit, float hint, int64_t n, int n_groups, const int32_t* dims,

@@ -76,6 +76,8 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         const int64_t w0 = local * S.unit;
         const uint8_t* mask = S.sched == kSchedMasked ? S.mask : nullptr;
         switch (S.unit) {
+        case 32: nrows = build_rows_window<32>(mask, S.n, w0, s_row, lane); break;
+        case 64: nrows = build_rows_window<64>(mask, S.n, w0, s_row, lane); break;
         case 128: nrows = build_rows_window<128>(mask, S.n, w0, s_row, lane); break;
         case 256: nrows = build_rows_window<256>(mask, S.n, w0, s_row, lane); break;
         default: nrows = build_rows_window<512>(mask, S.n, w0, s_row, lane); break;

@@ -382,16 +382,18 @@ template <int UNIT>
 __device__ __forceinline__ int build_rows_window(const uint8_t* mask, int64_t n, int64_t w0, int* s_row,
                                                  int lane)
 {
-    bool vis[UNIT / kWave];
+    // a 32-primitive window leaves the upper half-wave idle
+    constexpr int R = (UNIT + kWave - 1) / kWave;
+    bool vis[R];
 #pragma unroll
-    for (int b = 0; b < UNIT / kWave; ++b) {
+    for (int b = 0; b < R; ++b) {
         const int64_t i = w0 + b * kWave + lane;
-        vis[b] = i < n;
+        vis[b] = b * kWave + lane < UNIT && i < n;
         if (mask != nullptr && vis[b]) vis[b] = mask[i] != 0;
     }
     int nrows = 0;
 #pragma unroll
-    for (int b = 0; b < UNIT / kWave; ++b) {
+    for (int b = 0; b < R; ++b) {
         const uint64_t bal = __ballot(vis[b]);
         if (vis[b]) s_row[nrows + lanes_below(bal)] = (int)(w0 + b * kWave + lane);
         nrows += __popcll(bal);

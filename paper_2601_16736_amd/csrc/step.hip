@@ -94,6 +94,8 @@ StepFn pick(int sched, int unit)
     }
     if (sched == kSchedMasked) {
         switch (unit) {
+        case 32: return step_kernel<BF16, kSchedMasked, 32, NOISE>;
+        case 64: return step_kernel<BF16, kSchedMasked, 64, NOISE>;
         case 128: return step_kernel<BF16, kSchedMasked, 128, NOISE>;
         case 256: return step_kernel<BF16, kSchedMasked, 256, NOISE>;
         case 512: return step_kernel<BF16, kSchedMasked, 512, NOISE>;
@@ -102,6 +104,7 @@ StepFn pick(int sched, int unit)
     }
     if (sched == kSchedDense) {
         switch (unit) {
+        case 64: return step_kernel<BF16, kSchedDense, 64, NOISE>;
         case 256: return step_kernel<BF16, kSchedDense, 256, NOISE>;
         case 512: return step_kernel<BF16, kSchedDense, 512, NOISE>;
         default: return nullptr;

@@ -147,8 +147,10 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
     h.eps = 1e-15f;
 
     struct Cand { int sched, unit; };
-    const Cand cands[] = {{kSchedCompacted, 32}, {kSchedCompacted, 64}, {kSchedCompacted, 128}, {kSchedCompacted, 256},
-                          {kSchedCompacted, 512}, {kSchedMasked, 128}, {kSchedMasked, 256}, {kSchedMasked, 512}};
+    const Cand cands[] = {{kSchedCompacted, 32}, {kSchedCompacted, 64}, {kSchedCompacted, 128},
+                          {kSchedCompacted, 256}, {kSchedCompacted, 512}, {kSchedMasked, 32},
+                          {kSchedMasked, 64},     {kSchedMasked, 128},    {kSchedMasked, 256},
+                          {kSchedMasked, 512}};
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);

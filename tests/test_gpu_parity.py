@@ -169,7 +169,7 @@ def test_compact_matches_nonzero(p, n):
 
 # ---------------------------------------------------------------- one step
 SCHEDS = [(gs.GS_SCHED_COMPACTED, u) for u in (32, 64, 128, 256, 512)] + \
-         [(gs.GS_SCHED_MASKED, u) for u in (128, 256, 512)] + [(gs.GS_SCHED_DENSE, u) for u in (256, 512)]
+         [(gs.GS_SCHED_MASKED, u) for u in (32, 64, 128, 256, 512)] + [(gs.GS_SCHED_DENSE, u) for u in (64, 256, 512)]
 LAYOUTS = {"59": synth.GROUPS_59, "60split": synth.GROUPS_60_SPLIT}
 MOMENTS = {"f32": (False, False), "bf16_rne": (True, False), "bf16_sr": (True, True)}
 
