@@ -488,9 +488,16 @@ def main(argv=None) -> int:
                     help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="only run the 6M MCMC-shaped workload with relocation (for profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 16-scene batched workload (for profiling)")
     args = ap.parse_args(argv)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.batched_only:
+        import torch
+        import paper_2601_16736_amd as gs
+        print(json.dumps(run_batched(gs, torch)), flush=True)
+        return 0
     if args.mcmc_only:
         import torch
         import paper_2601_16736_amd as gs

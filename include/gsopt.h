@@ -279,7 +279,7 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
                              const gs_step_config* cfg, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Many scenes in one persistent launch.
+ * Many scenes in one launch.
  * ---------------------------------------------------------------------- */
 typedef struct {
     const gs_group* groups;  /* host array of n_groups descriptors (device arrays inside) */
@@ -299,9 +299,9 @@ typedef struct gs_batch gs_batch;
 /*
  * Builds a plan for 1..64 scenes whose moments are all stored as
  * moment_dtype: validates them, picks each scene's schedule (and wave unit),
- * uploads the scene table to device memory and sizes a persistent grid from
- * the kernel's occupancy.  Allocates (device table, two work-queue counters)
- * and synchronizes the device; the step calls below do not allocate.  The
+ * uploads the scene table to device memory and lays out each scene's range
+ * of work units.  Allocates the device table and synchronizes the device;
+ * the step calls below do not allocate.  The
  * arrays the scenes point to must stay alive and in place while the plan is
  * used; vis_count values are read on the device at each step.
  */
@@ -313,11 +313,13 @@ gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, int32_t mome
  * RSR samples and rounding draws are independent); the results are bit for
  * bit those of the per-scene calls.  cfg->schedule, cfg->unit and
  * cfg->visible_hint are ignored (the plan fixed them); cfg->moment_dtype must
- * equal the plan's.  One persistent kernel serves every scene's step units
- * and, when RSR runs, every scene's Re-State windows, pulling them from a
- * work queue; it is replayed from a HIP graph (the first call instantiates
- * it, later calls only replace its arguments).  Calls on one plan must not
- * overlap in time: they share the plan's work-queue counters.
+ * equal the plan's.  One kernel launch serves every scene's step units and,
+ * when Re-State or AIU runs, every scene's windows of invisible rows: each
+ * wave takes one unit and finds its scene from the plan's unit ranges.  It
+ * is replayed from a HIP graph (the first call instantiates it, later calls
+ * only replace its arguments and grid).  Calls on one plan may be issued
+ * back to back on one stream; from several host threads at once they race
+ * on the plan's host-side argument buffers.
  */
 gs_status adamw_gs_step_batched(gs_batch* batch, const gs_step_config* cfg, hipStream_t stream);
 

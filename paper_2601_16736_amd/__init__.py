@@ -339,7 +339,7 @@ class Scene:
 
 
 class Batch:
-    """Plan for stepping many scenes in one persistent launch."""
+    """Plan for stepping many scenes in one launch."""
 
     def __init__(self, scenes: Sequence[Scene], moment_dtype: int = GS_MOMENT_F32):
         self._scenes = list(scenes)              # keeps tensors alive

@@ -1,14 +1,16 @@
-// Many scenes in one persistent launch.
+// Many scenes in one launch.
 //
-// A plan holds the scenes' kernel views in device memory.  Each step is one
-// launch of a persistent grid (sized from the kernel's occupancy) whose waves
-// pull work units from a global atomic counter: first every scene's step
-// units (index-list slices or mask windows, per the scene's schedule), then,
-// on Re-State or AIU iterations, every scene's windows of invisible sampled
-// rows.
-// The last wave to finish resets the counters, so consecutive launches need
-// no clearing.  The launch is a HIP graph with one kernel node whose
-// arguments (the step's scalars) are replaced before each replay.
+// A plan holds the scenes' kernel views in device memory and, in the kernel
+// arguments, each scene's first work unit: first every scene's step units
+// (index-list slices or mask windows, per the scene's schedule), then, on
+// Re-State or AIU iterations, every scene's windows of invisible sampled
+// rows.  One wave takes one unit and finds its scene from those prefix sums
+// (at most 64 of them), so the launch needs no queue, no atomics and no
+// clearing between steps.  A compacted scene is given units for all its
+// primitives; waves past its visible count exit at once.  The launch is a
+// HIP graph with one kernel node whose arguments (the step's scalars and the
+// grid, which grows on Re-State iterations) are replaced before each replay.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -27,35 +29,21 @@ gs_status resolve_schedule(int requested, int unit, float hint, int64_t n, int n
 
 namespace {
 
-constexpr int kMaxScenes = kWave;     // one lane per scene when counting units
+constexpr int kMaxScenes = 64;
 constexpr int kBatchCap = 512;
 constexpr int kInvWindow = 512;
-// items per lane per trip in the step units: the persistent kernel keeps its
-// register budget at two (four would spill)
+// items per lane per trip in the step units (four would spill here)
 constexpr int kBatchUnroll = 2;
+constexpr int kBatchMinWindow = 128;   // smallest masked window in a plan
+constexpr int kBatchMinSlice = 64;     // smallest compacted slice in a plan
 
 struct KBatch {
     const KScene* scenes;
     int32_t n_scenes;
-    int32_t inv;          // units of invisible sampled rows (Re-State or AIU) this step
-    int32_t* queue;       // [0] next unit, [1] waves finished
-    int32_t total_waves;
-    int32_t pad;
+    int32_t inv;                              // 1: invisible units follow the step units
+    int32_t step_first[kMaxScenes + 1];       // first step unit of each scene; [n_scenes] = total
+    int32_t inv_first[kMaxScenes + 1];        // first invisible unit of each scene, after all step units
 };
-
-__device__ __forceinline__ int scene_step_units(const KScene& S)
-{
-    if (S.sched == kSchedCompacted) {
-        const int cnt = (int)min((int64_t)*S.count, S.n);
-        return cnt > 0 ? (cnt + S.unit - 1) / S.unit : 0;
-    }
-    return (int)((S.n + S.unit - 1) / S.unit);
-}
-
-__device__ __forceinline__ int scene_inv_units(const KScene& S, int inv)
-{
-    return (inv && S.sched != kSchedDense && S.mask != nullptr) ? (int)((S.n + kInvWindow - 1) / kInvWindow) : 0;
-}
 
 template <bool BF16, bool NOISE>
 __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, float* s_rb1,
@@ -109,6 +97,14 @@ __device__ __forceinline__ void invisible_unit(const KScene& S, const KHyper& H,
     wave_sync();
 }
 
+// The scene of unit u: the last s with first[s] <= u (first[] ascending).
+__device__ __forceinline__ int scene_of(const int32_t* first, int n_scenes, int64_t u)
+{
+    int s = 0;
+    while (s + 1 < n_scenes && first[s + 1] <= u) ++s;
+    return s;
+}
+
 template <bool BF16, bool NOISE>
 __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
 {
@@ -117,45 +113,15 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
     __shared__ float s_rsb2[kWavesPerBlock][kBatchCap];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-
-    // units of scene `lane`, and their running total over the scenes
-    int su = 0, ru = 0;
-    if (lane < B.n_scenes) {
-        const KScene& S = B.scenes[lane];
-        su = scene_step_units(S);
-        ru = scene_inv_units(S, B.inv);
-    }
-    const int mine = su + ru;
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
-    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
-
-    for (;;) {
-        int u = 0;
-        if (lane == 0) u = atomicAdd(&B.queue[0], 1);
-        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
-        if (u >= total) break;
-        const uint64_t owner = __ballot(lane < B.n_scenes && incl > u);
-        const int s = __ffsll((unsigned long long)owner) - 1;
-        const int start = __builtin_amdgcn_readfirstlane(__shfl(incl - mine, s));
-        const int steps_s = __builtin_amdgcn_readfirstlane(__shfl(su, s));
-        const KScene& S = B.scenes[s];
-        const int local = u - start;
-        if (local < steps_s) step_unit<BF16, NOISE>(S, H, local, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
-        else invisible_unit<BF16>(S, H, local - steps_s, s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
-    }
-
-    // every wave checks out; the last one resets the counters for the next launch
-    if (lane == 0) {
-        const int done = atomicAdd(&B.queue[1], 1);
-        if (done == B.total_waves - 1) {
-            atomicExch(&B.queue[0], 0);
-            atomicExch(&B.queue[1], 0);
-        }
+    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t steps = B.step_first[B.n_scenes];
+    if (u < steps) {
+        const int s = scene_of(B.step_first, B.n_scenes, u);
+        step_unit<BF16, NOISE>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+    } else if (B.inv && u - steps < B.inv_first[B.n_scenes]) {
+        const int64_t v = u - steps;
+        const int s = scene_of(B.inv_first, B.n_scenes, v);
+        invisible_unit<BF16>(B.scenes[s], H, v - B.inv_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
     }
 }
 
@@ -172,9 +138,7 @@ struct gs_batch {
     std::vector<KScene> h_scenes;
     std::vector<int32_t> sched;
     KScene* d_scenes = nullptr;
-    int32_t* d_queue = nullptr;
-    int grid[2] = {0, 0};                // per kernel variant: [0] plain, [1] position noise
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};   // per kernel variant: [0] plain, [1] position noise
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraphNode_t node[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
@@ -202,7 +166,6 @@ void free_batch(gs_batch* b)
     }
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->d_scenes) (void)hipFree(b->d_scenes);
-    if (b->d_queue) (void)hipFree(b->d_queue);
     delete b;
 }
 
@@ -258,6 +221,11 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
             free_batch(b);
             return st;
         }
+        // a wave reads its scene's descriptors from device memory, a fixed
+        // cost per unit that the smallest windows of one-scene launches do
+        // not amortise
+        if (sched == kSchedMasked) unit = std::max(unit, kBatchMinWindow);
+        if (sched == kSchedCompacted) unit = std::max(unit, kBatchMinSlice);
         K.sched = sched;
         K.unit = unit;
         K.seed_offset = s;
@@ -267,28 +235,28 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
         K.t = sc.step_count;
         b->sched[(size_t)s] = sched;
     }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return fail_batch(b, GS_EHIP, "gs_batch_create: device query failed");
-    for (int v = 0; v < 2; ++v) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(kernel_for(moment_dtype, v)), kBlock, 0) != hipSuccess)
-            return fail_batch(b, GS_EHIP, "gs_batch_create: occupancy query failed");
-        b->grid[v] = std::max(1, cus * std::max(1, per_cu));
+    // each scene's first unit: step units (for a compacted scene, enough for
+    // all its primitives), then the windows of its invisible rows
+    int64_t acc = 0, acc_inv = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        const KScene& K = b->h_scenes[(size_t)s];
+        b->kb.step_first[s] = (int32_t)acc;
+        b->kb.inv_first[s] = (int32_t)acc_inv;
+        acc += K.n > 0 ? (K.n + K.unit - 1) / K.unit : 0;
+        if (K.sched != kSchedDense && K.mask != nullptr) acc_inv += (K.n + kInvWindow - 1) / kInvWindow;
+        if (acc + acc_inv >= ((int64_t)1 << 31) - kWavesPerBlock)
+            return fail_batch(b, GS_EINVAL, "gs_batch_create: too many work units in one plan");
     }
-    if (hipMalloc(&b->d_scenes, sizeof(KScene) * (size_t)n_scenes) != hipSuccess ||
-        hipMalloc(&b->d_queue, 2 * sizeof(int32_t)) != hipSuccess)
+    b->kb.step_first[n_scenes] = (int32_t)acc;
+    b->kb.inv_first[n_scenes] = (int32_t)acc_inv;
+    if (hipMalloc(&b->d_scenes, sizeof(KScene) * (size_t)n_scenes) != hipSuccess)
         return fail_batch(b, GS_ENOMEM, "gs_batch_create: hipMalloc failed");
     if (hipMemcpy(b->d_scenes, b->h_scenes.data(), sizeof(KScene) * (size_t)n_scenes, hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemset(b->d_queue, 0, 2 * sizeof(int32_t)) != hipSuccess || hipEventCreate(&b->done) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess)
+        hipEventCreate(&b->done) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return fail_batch(b, GS_EHIP, "gs_batch_create: upload failed");
     b->kb.scenes = b->d_scenes;
     b->kb.n_scenes = n_scenes;
-    b->kb.queue = b->d_queue;
     *out = b;
     return GS_OK;
 }
@@ -320,17 +288,21 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
                 return set_error(GS_EINVAL, "adamw_gs_step_batched: RSR or AIU needs every sparse scene's "
                                             "visibility mask (to find invisible rows)");
     // Each variant has its own graph: a kernel node keeps the function it
-    // was created with, and the wave count that resets the queue is the
-    // variant's own grid.
+    // was created with.  The grid covers the step units, plus the invisible
+    // windows on Re-State or AIU iterations.
     const int v = h.noise ? 1 : 0;
     b->kh = h;
     b->kb.inv = (h.rsr_thr > 0 || h.aiu_thr > 0) ? 1 : 0;
-    b->kb.total_waves = b->grid[v] * kWavesPerBlock;
+    const int64_t units = (int64_t)b->kb.step_first[b->n_scenes] + (b->kb.inv ? b->kb.inv_first[b->n_scenes] : 0);
+    if (units == 0) {
+        const hipError_t e = hipEventRecord(b->done, stream);
+        return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
+    }
     void* args[] = {&b->kb, &b->kh};
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
     p.func = kernel_for(b->moment_dtype, v);
-    p.gridDim = dim3((unsigned)b->grid[v]);
+    p.gridDim = dim3((unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock));
     p.blockDim = dim3(kBlock);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
