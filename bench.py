@@ -347,13 +347,14 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8)
         state = [dict(groups=make_groups(sc, mdt), t=torch.zeros(sc["n"], dtype=torch.int32, device=dev))
                  for sc in scenes]
         plans = []
-        if form == "batched_bf16":
+        if form.startswith("batched_bf16"):
             for r in range(n_masks):
                 plans.append(gs.Batch([gs.Scene(groups=st["groups"], n=sc["n"], step_count=st["t"],
                                                 visible=sc["masks"][r], vis_idx=sc["idx"][r],
                                                 vis_count=sc["cnt"][r], schedule=sc["sched"],
                                                 visible_hint=sc["p"]) for sc, st in zip(scenes, state)],
                                       moment_dtype=mom))
+                plans[-1].set_resident(form.endswith("resident"))
 
         def one(k):
             r = k % n_masks
@@ -392,7 +393,7 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8)
            "schedules": {"compacted": sum(sc["sched"] == gs.GS_SCHED_COMPACTED for sc in scenes),
                          "masked": sum(sc["sched"] == gs.GS_SCHED_MASKED for sc in scenes)},
            "visible_per_step": vis_total / steps}
-    for form in ("batched_bf16", "per_scene_bf16", "per_scene_f32"):
+    for form in ("batched_bf16", "batched_bf16_resident", "per_scene_bf16", "per_scene_f32"):
         wall = timed(form)
         out[form] = {"value": vis_total * 59 / wall, "ms_per_step": wall / steps * 1e3}
     scenes.clear()

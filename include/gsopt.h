@@ -323,6 +323,15 @@ gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, int32_t mome
  */
 gs_status adamw_gs_step_batched(gs_batch* batch, const gs_step_config* cfg, hipStream_t stream);
 
+/*
+ * Launch shape of the plan's steps.  resident = 0 (the default): one wave
+ * per work unit, the hardware dispatcher balancing them.  resident = 1: a
+ * persistent grid of as many blocks as the device holds at once, whose
+ * waves stride over the work units.  Results are the same bits either way.
+ * Takes effect at the next adamw_gs_step_batched call.
+ */
+gs_status gs_batch_set_resident(gs_batch* batch, int32_t resident);
+
 /* Schedule chosen for scene s of the plan (GS_SCHED_*), or -1. */
 int32_t gs_batch_scene_schedule(const gs_batch* batch, int32_t s);
 

@@ -105,6 +105,8 @@ _lib.gs_batch_create.restype = _i32
 _lib.gs_batch_create.argtypes = [ctypes.POINTER(gs_scene), _i32, _i32, ctypes.POINTER(_vp)]
 _lib.adamw_gs_step_batched.restype = _i32
 _lib.adamw_gs_step_batched.argtypes = [_vp, ctypes.POINTER(gs_step_config), _vp]
+_lib.gs_batch_set_resident.restype = _i32
+_lib.gs_batch_set_resident.argtypes = [_vp, _i32]
 _lib.gs_batch_scene_schedule.restype = _i32
 _lib.gs_batch_scene_schedule.argtypes = [_vp, _i32]
 _lib.gs_batch_destroy.restype = _i32
@@ -134,7 +136,8 @@ _lib.gs_append.restype = _i32
 _lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64, _vp, _vp]
 
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_visibility_multi", "gs_compact",
-            "adamw_gs_step", "adamw_gs_step_view", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_scene_schedule", "gs_batch_destroy",
+            "adamw_gs_step", "adamw_gs_step_view", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_set_resident", "gs_batch_scene_schedule",
+            "gs_batch_destroy",
             "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
             "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
             "gs_prune", "gs_append"]
@@ -362,6 +365,10 @@ class Batch:
 
     def schedule(self, s: int) -> int:
         return int(_lib.gs_batch_scene_schedule(self._h, s))
+
+    def set_resident(self, resident: bool) -> None:
+        """Persistent grid (True) or one wave per unit (False, the default)."""
+        _check(_lib.gs_batch_set_resident(self._h, int(bool(resident))))
 
     def step(self, cfg: StepConfig, stream=None) -> None:
         adamw_gs_step_batched(self, cfg, stream)

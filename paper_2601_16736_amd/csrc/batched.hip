@@ -4,9 +4,11 @@
 // arguments, each scene's first work unit: first every scene's step units
 // (index-list slices or mask windows, per the scene's schedule), then, on
 // Re-State or AIU iterations, every scene's windows of invisible sampled
-// rows.  One wave takes one unit and finds its scene from those prefix sums
-// (at most 64 of them), so the launch needs no queue, no atomics and no
-// clearing between steps.  A compacted scene is given units for all its
+// rows.  A wave takes a unit and finds its scene from those prefix sums (at
+// most 64 of them), so the launch needs no queue, no atomics and no clearing
+// between steps.  By default the grid has one wave per unit; a resident
+// (persistent) grid sized to the device's occupancy, whose waves stride over
+// the units, is the other choice (gs_batch_set_resident).  A compacted scene is given units for all its
 // primitives; waves past its visible count exit at once.  The launch is a
 // HIP graph with one kernel node whose arguments (the step's scalars and the
 // grid, which grows on Re-State iterations) are replaced before each replay.
@@ -36,6 +38,7 @@ constexpr int kInvWindow = 512;
 constexpr int kBatchUnroll = 2;
 constexpr int kBatchMinWindow = 128;   // smallest masked window in a plan
 constexpr int kBatchMinSlice = 64;     // smallest compacted slice in a plan
+
 
 struct KBatch {
     const KScene* scenes;
@@ -113,15 +116,19 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
     __shared__ float s_rsb2[kWavesPerBlock][kBatchCap];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     const int64_t steps = B.step_first[B.n_scenes];
-    if (u < steps) {
-        const int s = scene_of(B.step_first, B.n_scenes, u);
-        step_unit<BF16, NOISE>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
-    } else if (B.inv && u - steps < B.inv_first[B.n_scenes]) {
-        const int64_t v = u - steps;
-        const int s = scene_of(B.inv_first, B.n_scenes, v);
-        invisible_unit<BF16>(B.scenes[s], H, v - B.inv_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+    const int64_t total = steps + (B.inv ? B.inv_first[B.n_scenes] : 0);
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave; u < total; u += stride) {
+        if (u < steps) {
+            const int s = scene_of(B.step_first, B.n_scenes, u);
+            step_unit<BF16, NOISE>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave],
+                                   lane);
+        } else {
+            const int64_t v = u - steps;
+            const int s = scene_of(B.inv_first, B.n_scenes, v);
+            invisible_unit<BF16>(B.scenes[s], H, v - B.inv_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+        }
     }
 }
 
@@ -138,6 +145,7 @@ struct gs_batch {
     std::vector<KScene> h_scenes;
     std::vector<int32_t> sched;
     KScene* d_scenes = nullptr;
+    int64_t persistent_blocks = 0;              // > 0: a resident grid whose waves loop over the units
     hipGraph_t graph[2] = {nullptr, nullptr};   // per kernel variant: [0] plain, [1] position noise
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraphNode_t node[2] = {nullptr, nullptr};
@@ -302,7 +310,8 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
     p.func = kernel_for(b->moment_dtype, v);
-    p.gridDim = dim3((unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock));
+    const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    p.gridDim = dim3((unsigned)(b->persistent_blocks > 0 ? std::min<int64_t>(blocks, b->persistent_blocks) : blocks));
     p.blockDim = dim3(kBlock);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
@@ -318,6 +327,27 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     if (e == hipSuccess) e = hipGraphLaunch(b->exec[v], stream);
     if (e == hipSuccess) e = hipEventRecord(b->done, stream);
     if (e != hipSuccess) return set_error(GS_EHIP, hipGetErrorString(e));
+    return GS_OK;
+}
+
+extern "C" gs_status gs_batch_set_resident(gs_batch* b, int32_t resident)
+{
+    clear_error();
+    if (b == nullptr) return set_error(GS_EINVAL, "gs_batch_set_resident: batch is NULL");
+    if (!resident) {
+        b->persistent_blocks = 0;
+        return GS_OK;
+    }
+    // as many blocks as fit on the device at once (the plain variant's
+    // occupancy); the noise variant may fit fewer, which only makes some
+    // blocks start later
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(kernel_for(b->moment_dtype, 0)), kBlock, 0) != hipSuccess)
+        return set_error(GS_EHIP, "gs_batch_set_resident: device query failed");
+    b->persistent_blocks = (int64_t)cus * std::max(1, per_cu);
     return GS_OK;
 }
 

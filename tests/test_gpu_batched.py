@@ -46,8 +46,9 @@ def _noise_kw(on):
                 noise_t=0.5)     # opacities of these states spread around 0.5
 
 
-@pytest.mark.parametrize("bf16,noise", [(False, False), (True, False), (True, True)])
-def test_batched_equals_per_scene_calls(bf16, noise):
+@pytest.mark.parametrize("bf16,noise,resident", [(False, False, False), (True, False, False), (True, True, False),
+                                                  (True, False, True), (False, True, True)])
+def test_batched_equals_per_scene_calls(bf16, noise, resident):
     """noise=True switches position noise on every other replay, so one plan
     runs both of its kernel variants."""
     rng = np.random.default_rng(3)
@@ -66,6 +67,7 @@ def test_batched_equals_per_scene_calls(bf16, noise):
                        vis_idx=d["idx"], vis_count=d["cnt"], schedule=d["sched"], visible_hint=d["p"])
               for d in plans]
     batch = gs.Batch(scenes, moment_dtype=int(bf16))
+    batch.set_resident(resident)
     for s, d in enumerate(plans):
         assert batch.schedule(s) in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED, gs.GS_SCHED_DENSE)
     for it in range(5):                       # five replays of the plan's graph
