@@ -401,13 +401,17 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8)
     return out
 
 
-def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
+def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10, path: str = "two_launch", counts_from=None):
     """3DGS-MCMC-shaped workload: 6M primitives (the cap), means from an
     equal-weight mixture of 64 isotropic Gaussians (sigma 1.5), other
     attributes N(0, 1), opacity and scale regularisation weights 0.01, and
     every step the 1 % lowest opacity logits (60 000) get their state reset
-    (relocation).  Morton layout, FP32 moments.  One step = visibility +
-    compaction, the fused step, and the relocation select + reset."""
+    (relocation).  Morton layout, FP32 moments.  One step = the AdamW-GS step
+    ("two_launch": visibility + compaction, then the masked step; "view": the
+    fused view step) and the relocation select + reset.  The fused path
+    writes no count: its visible counts come from a two-launch run
+    (`counts_from`), whose end state it must reproduce bit for bit (the
+    returned digest)."""
     import synth
     dev = torch.device("cuda:0")
     n = 6_000_000
@@ -441,13 +445,17 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
 
     def one(k, slot=-1):
         cnt = counts[k:k + 1]
-        gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
         for G, sets in zip(groups, grads):
             G.grad = sets[k % 2]
-        gs.adamw_gs_step(groups, n, t, gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k,
-                                                     rsr_enable=(k % RSR_EVERY == 0), rsr_ratio=RSR_P,
-                                                     rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **STEP_LAUNCH),
-                         visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        common = dict(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0), rsr_ratio=RSR_P,
+                      rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2)
+        if path == "view":
+            gs.adamw_gs_step_view(groups, n, t, gs.StepConfig(**common, unit=VIEW_UNIT), groups[0].param,
+                                  gcams[order[k]], stream=stream)
+        else:
+            gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+            gs.adamw_gs_step(groups, n, t, gs.StepConfig(**common, **STEP_LAUNCH), visible=mask, vis_idx=idx,
+                             vis_count=cnt, stream=stream)
         if slot >= 0:
             ev.record("start", slot, stream)
         gs.gs_relocate_reset(opacity, k_reloc, groups, gs.GS_MOMENT_F32, t, True, rws, stream=stream)
@@ -462,15 +470,42 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10):
         one(warmup + j, j)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    nv = counts.cpu().numpy()[warmup:].astype(np.int64)
+    if path == "view":
+        if counts_from is None:
+            raise ValueError("the fused path needs the visible counts of a two-launch run")
+        all_counts = np.asarray(counts_from)
+    else:
+        all_counts = counts.cpu().numpy().astype(np.int64)
+    nv = all_counts[warmup:]
     reloc_us = float(np.mean([ev.ms(j) for j in range(steps)]) * 1e3)
     ev.close()
+    # exact digest of the end state: integer sums of the bit patterns
+    digest = [int(t.to(torch.int64).sum().item())]
+    for G in groups:
+        for a in (G.param, G.exp_avg, G.exp_avg_sq):
+            digest.append(int(a.view(torch.int32).to(torch.int64).sum().item()))
     del groups, params, grads, t, mask, idx, rws
     torch.cuda.empty_cache()
     return {"workload": "6M primitives, 64-cluster mixture means (sigma 1.5), lambda_o = lambda_s = 0.01, "
                         "1 %% lowest opacity reset every step, Morton order, FP32, %d steps" % steps,
-            "value": int(nv.sum()) * 59 / wall, "ms_per_step": wall / steps * 1e3,
-            "visible_frac": float(nv.mean() / n), "relocation_us": reloc_us}
+            "path": path, "value": int(nv.sum()) * 59 / wall, "ms_per_step": wall / steps * 1e3,
+            "visible_frac": float(nv.mean() / n), "relocation_us": reloc_us, "counts": all_counts,
+            "digest": digest}
+
+
+def run_mcmc_both(gs, torch, cams, steps: int = 500, warmup: int = 10):
+    """The MCMC-shaped workload on both paths; the fused run must end in the
+    two-launch run's state."""
+    two = run_mcmc(gs, torch, cams, steps, warmup, "two_launch")
+    view = run_mcmc(gs, torch, cams, steps, warmup, "view", counts_from=two["counts"])
+    view["same_state_as_two_launch"] = view["digest"] == two["digest"]
+    out = []
+    for r in (view, two):
+        r = dict(r)
+        r.pop("counts")
+        r.pop("digest")
+        out.append(r)
+    return out
 
 
 def main(argv=None) -> int:
@@ -503,7 +538,8 @@ def main(argv=None) -> int:
         import torch
         import paper_2601_16736_amd as gs
         import synth
-        print(json.dumps(run_mcmc(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup)), flush=True)
+        for r in run_mcmc_both(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup):
+            print(json.dumps(r), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the AdamW-GS step has no cross-GPU exchange to measure "
@@ -577,7 +613,9 @@ def main(argv=None) -> int:
         print("bench: variant batched 16 scenes", file=sys.stderr, flush=True)
         variants.append({"batched": run_batched(gs, torch)})
         print("bench: variant MCMC-shaped 6M with relocation", file=sys.stderr, flush=True)
-        variants.append({"mcmc_6m": run_mcmc(gs, torch, cams)})
+        view, two = run_mcmc_both(gs, torch, cams)
+        variants.append({"mcmc_6m": view})
+        variants.append({"mcmc_6m_two_launch": two})
 
     out = {
         "metric": "primitive-attr updates/s + % HBM roofline, fused AdamW-GS vs plain, 3M Gaussians",

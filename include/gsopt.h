@@ -353,7 +353,8 @@ size_t gs_relocate_workspace_size(int64_t n);
  * with reset_t also their step count.  key [n] FP32 device (finite values),
  * 0 <= k <= n.  selected [k] int32 out (ascending indices) or NULL.
  * workspace: device memory of gs_relocate_workspace_size(n) bytes, 256-byte
- * aligned; contents on entry are ignored.
+ * aligned; contents on entry are ignored.  key must not overlap any group's
+ * m or v, step_count or selected: rows are zeroed while keys are still read.
  */
 gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_group* groups,
                             int32_t n_groups, int32_t moment_dtype, int32_t* step_count,

@@ -5,9 +5,10 @@
 // Selection is a most-significant-digit radix select over the keys mapped to
 // order-preserving uint32: four 8-bit passes narrow the key of the k-th
 // smallest element (K) and the number r of elements equal to K that still
-// belong to the selection.  An ordered block scan then picks every key < K
-// and the first r keys == K in index order, writing the selected indices in
-// ascending order; a last kernel zeroes their state rows.
+// belong to the selection.  Per-block counts of keys < K and == K, summed
+// over the blocks before each block, let every block pick its keys < K and
+// the first r keys == K in index order, writing the selected indices in
+// ascending order and zeroing their state rows.
 #include <cstring>
 
 #include "device_common.h"
@@ -22,6 +23,13 @@ namespace {
 constexpr int kRelPerThread = 16;
 constexpr int kRelPerBlock = kBlock * kRelPerThread;   // 4096 keys per block
 constexpr size_t kAlign = 256;
+// Each digit pass accumulates its histogram into kHistCopies global copies,
+// one per XCD under the round-robin dispatch of blocks, kHistStride words
+// apart: one shared copy serialises thousands of device-scope atomics on a
+// few cache lines, and that, not the key reads, set the time of a pass.
+constexpr int kHistCopies = 8;
+constexpr int kHistStride = 1024;
+constexpr int kHistWords = 4 * kHistCopies * kHistStride;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -41,28 +49,36 @@ __device__ __forceinline__ uint32_t key_ord(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// st[0] = the initial state; the four pass histograms cleared.  256 threads.
+// st[0] = the initial state; every copy of the four pass histograms
+// cleared.  One block of 256 threads per (pass, copy).
 __global__ void select_init_kernel(SelectState* st, uint32_t* hist, int32_t k)
 {
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         st[0].prefix = 0u;
         st[0].mask = 0u;
         st[0].rank = k;
         st[0].pad = 0;
     }
-    for (int p = 0; p < 4; ++p) hist[p * 256 + threadIdx.x] = 0u;
+    hist[blockIdx.x * kHistStride + threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ uint32_t* pass_hist(uint32_t* hist, int pass, int copy)
+{
+    return hist + (pass * kHistCopies + copy) * kHistStride;
 }
 
 // The state after a digit pass, from the state before it and the pass's
-// histogram: the bucket where the running count first reaches `rank` fixes
-// the digit.  Every block of the next kernel computes it (a 1 KB read and a
-// 256-wide scan), so no kernel waits on another block; block 0 records it.
-// Needs all 256 threads of the block.
-__device__ SelectState narrow(const SelectState* prev, const uint32_t* hist, int shift)
+// histogram copies: the bucket where the running count first reaches `rank`
+// fixes the digit.  Every block of the next kernel computes it (8 KB read
+// from L2 and a 256-wide scan), so no kernel waits on another block; block 0
+// records it.  Needs all 256 threads of the block.
+__device__ SelectState narrow(const SelectState* prev, uint32_t* hist, int pass, int shift)
 {
     __shared__ uint32_t s_inc[256];
     __shared__ SelectState s_st;
-    const uint32_t c = hist[threadIdx.x];
+    uint32_t c = 0;
+#pragma unroll
+    for (int cp = 0; cp < kHistCopies; ++cp) c += pass_hist(hist, pass, cp)[threadIdx.x];
     s_inc[threadIdx.x] = c;
     if (threadIdx.x == 0) s_st = *prev;
     __syncthreads();
@@ -106,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     uint32_t o[kRelPerThread];
     load_keys(key, n, first, o);
     const int shift = 24 - 8 * pass;
-    const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist + (pass - 1) * 256, shift + 8);
+    const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist, pass - 1, shift + 8);
     if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
     __syncthreads();
     uint32_t* mine = s_hist[threadIdx.x / kWave];
@@ -118,17 +134,17 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     __syncthreads();
     uint32_t c = 0;
     for (int w = 0; w < kWavesPerBlock; ++w) c += s_hist[w][threadIdx.x];
-    if (c) atomicAdd(&hist[pass * 256 + threadIdx.x], c);
+    if (c) atomicAdd(&pass_hist(hist, pass, blockIdx.x % kHistCopies)[threadIdx.x], c);
 }
 
 // Per block: keys below K and keys equal to K, K being the key of the k-th
 // smallest (the state after the last pass, recorded in st[4] by block 0).
 __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __restrict__ key, int64_t n,
-                                                              SelectState* st, const uint32_t* hist, int32_t* lt,
+                                                              SelectState* st, uint32_t* hist, int32_t* lt,
                                                               int32_t* eq)
 {
     __shared__ int s_lt[kWavesPerBlock], s_eq[kWavesPerBlock];
-    const SelectState fin = narrow(&st[3], hist + 3 * 256, 0);
+    const SelectState fin = narrow(&st[3], hist, 3, 0);
     if (blockIdx.x == 0 && threadIdx.x == 0) st[4] = fin;
     const uint32_t K = fin.prefix;
     const bool any = fin.rank > 0;
@@ -203,85 +219,169 @@ __global__ void select_scan_kernel(int32_t* lt, int32_t* eq, int nblocks)
     }
 }
 
-// Per block, in index order: take every key < K and the first `rank` keys
-// equal to K; write their indices at their place in the ascending list.
-__global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __restrict__ key, int64_t n,
-                                                              const SelectState* st, const int32_t* lt_before,
-                                                              const int32_t* eq_before, int32_t* sel)
+// Up to this many blocks, each block of the write kernel sums the counts of
+// the blocks before it itself (at most 16 KB of L2 reads) instead of a
+// separate single-block scan kernel, whose run is mostly latency.
+constexpr int kInlineScanBlocks = 2048;
+
+// Sum over blocks j < blockIdx.x of lt[j] and eq[j].  Needs all threads.
+__device__ __forceinline__ void counts_before(const int32_t* lt, const int32_t* eq, int* a_out, int* b_out)
 {
-    __shared__ int s_cnt[2][kWavesPerBlock];
-    __shared__ int s_run_eq, s_run_sel;
+    __shared__ int s_a[kWavesPerBlock], s_b[kWavesPerBlock];
+    int a = 0, b = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) {
+        a += lt[j];
+        b += eq[j];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    if (threadIdx.x % kWave == 0) {
+        s_a[threadIdx.x / kWave] = a;
+        s_b[threadIdx.x / kWave] = b;
+    }
+    __syncthreads();
+    a = 0;
+    b = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        a += s_a[w];
+        b += s_b[w];
+    }
+    *a_out = a;
+    *b_out = b;
+}
+
+// Zeroes m and v of the wave's staged rows in every group, walking each
+// group's flattened (row, chunk) space like the step does, so consecutive
+// lanes clear consecutive chunks of a row even for 1- and 3-element groups.
+template <bool BF16, int V>
+__device__ __forceinline__ void zero_group(const KGroup& G, int nrows, const int* s_row, int lane)
+{
+    const int cpr = G.cpr;
+    const int items = nrows * cpr;
+    int r = lane / cpr;
+    int c = lane - r * cpr;
+    const int dr = kWave / cpr;
+    const int dc = kWave - dr * cpr;
+    const float zf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t zh[4] = {0u, 0u, 0u, 0u};
+    for (int k = lane; k < items; k += kWave) {
+        const int64_t e = (int64_t)s_row[r] * G.dim + c * V;
+        if constexpr (BF16) {
+            store_h<V>(static_cast<uint16_t*>(G.m) + e, zh);
+            store_h<V>(static_cast<uint16_t*>(G.v) + e, zh);
+        } else {
+            store_f<V>(static_cast<float*>(G.m) + e, zf);
+            store_f<V>(static_cast<float*>(G.v) + e, zf);
+        }
+        r += dr;
+        c += dc;
+        if (c >= cpr) { c -= cpr; ++r; }
+    }
+}
+
+// Per block, in index order: take every key < K and the first `rank` keys
+// equal to K; write their indices at their place in the ascending list (if
+// sel is given) and zero their state rows.  Key (round j, wave w, lane l) of
+// the block is element first + 256 j + 64 w + l, so index order is round,
+// then wave, then lane: the wave ballots of all rounds are taken first and
+// two barriers give every wave its offsets.  INLINE: lt / eq are the
+// per-block counts, summed here; else their exclusive scans.
+template <bool INLINE, bool BF16>
+__global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __restrict__ key, int64_t n,
+                                                              const SelectState* st, const int32_t* lt,
+                                                              const int32_t* eq, int32_t* sel, KScene S,
+                                                              int reset_t)
+{
+    constexpr int J = kRelPerThread;
+    __shared__ int s_eq[J][kWavesPerBlock], s_sel[J][kWavesPerBlock];
+    __shared__ int s_row[kWavesPerBlock][J * kWave];
     const uint32_t K = st[4].prefix;
     const int rank = st[4].rank;
     if (rank <= 0) return;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
-    const int eq0 = eq_before[blockIdx.x];
-    // selected before this block: all smaller keys, plus the equal ones that fit
-    const int sel0 = lt_before[blockIdx.x] + min(eq0, rank);
-    if (threadIdx.x == 0) {
-        s_run_eq = 0;
-        s_run_sel = 0;
-    }
-    uint32_t o[kRelPerThread];
+    uint32_t o[J];
     load_keys(key, n, first, o);
-    __syncthreads();
+    int lt0, eq0;
+    if constexpr (INLINE) {
+        counts_before(lt, eq, &lt0, &eq0);
+    } else {
+        lt0 = lt[blockIdx.x];
+        eq0 = eq[blockIdx.x];
+    }
+    // selected before this block: all smaller keys, plus the equal ones that fit
+    const int sel0 = lt0 + min(eq0, rank);
+
+    uint64_t b_eq[J];
 #pragma unroll
-    for (int j = 0; j < kRelPerThread; ++j) {
-        const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
-        const bool is_eq = i < n && o[j] == K;
-        const bool is_lt = i < n && o[j] < K;
-        const uint64_t b_eq = __ballot(is_eq);
-        if (lane == 0) s_cnt[0][wave] = __popcll(b_eq);
-        __syncthreads();
-        int eq_off = s_run_eq;
-        for (int w = 0; w < wave; ++w) eq_off += s_cnt[0][w];
-        const int my_eq_rank = eq0 + eq_off + lanes_below(b_eq);
-        const bool pick = is_lt || (is_eq && my_eq_rank < rank);
-        const uint64_t b_sel = __ballot(pick);
-        if (lane == 0) s_cnt[1][wave] = __popcll(b_sel);
-        __syncthreads();
-        int sel_off = s_run_sel;
-        for (int w = 0; w < wave; ++w) sel_off += s_cnt[1][w];
-        if (pick && sel != nullptr) sel[sel0 + sel_off + lanes_below(b_sel)] = (int32_t)i;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 0; w < kWavesPerBlock; ++w) {
-                s_run_eq += s_cnt[0][w];
-                s_run_sel += s_cnt[1][w];
-            }
+    for (int j = 0; j < J; ++j) {
+        const bool in = first + (int64_t)j * kBlock + threadIdx.x < n;
+        b_eq[j] = __ballot(in && o[j] == K);
+        if (lane == 0) s_eq[j][wave] = __popcll(b_eq[j]);
+    }
+    __syncthreads();
+    uint32_t picks = 0;
+    uint64_t b_sel[J];
+    int run = eq0;   // equal keys before round j
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const bool in = first + (int64_t)j * kBlock + threadIdx.x < n;
+        int off = run, tot = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            const int c = s_eq[j][w];
+            off += w < wave ? c : 0;
+            tot += c;
         }
-        __syncthreads();
+        run += tot;
+        const bool is_eq = (b_eq[j] >> lane) & 1u;
+        const bool pick = (in && o[j] < K) || (is_eq && off + lanes_below(b_eq[j]) < rank);
+        picks |= (uint32_t)pick << j;
+        b_sel[j] = __ballot(pick);
+        if (lane == 0) s_sel[j][wave] = __popcll(b_sel[j]);
+    }
+    __syncthreads();
+    run = sel0;
+    int nrows = 0;   // the wave's picks, staged in index order
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        int off = run, tot = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            const int c = s_sel[j][w];
+            off += w < wave ? c : 0;
+            tot += c;
+        }
+        run += tot;
+        if ((picks >> j) & 1u) {
+            const int32_t i = (int32_t)(first + (int64_t)j * kBlock + threadIdx.x);
+            if (sel != nullptr) sel[off + lanes_below(b_sel[j])] = i;
+            s_row[wave][nrows + lanes_below(b_sel[j])] = i;
+            if (reset_t && S.t != nullptr) S.t[i] = 0;
+        }
+        nrows += __popcll(b_sel[j]);
+    }
+    if (nrows == 0) return;
+    wave_sync();
+    for (int gi = 0; gi < S.n_groups; ++gi) {
+        const KGroup& G = S.g[gi];
+        if (G.vec == 4) zero_group<BF16, 4>(G, nrows, s_row[wave], lane);
+        else if (G.vec == 2) zero_group<BF16, 2>(G, nrows, s_row[wave], lane);
+        else zero_group<BF16, 1>(G, nrows, s_row[wave], lane);
     }
 }
 
-// Zeroes m and v of the selected rows in every group, and t if asked.
-// One wave per selected row at a time: its lanes clear the row's elements
-// group by group (no index arithmetic beyond the row base).
-template <bool BF16>
-__global__ __launch_bounds__(kBlock) void reset_rows_kernel(KScene S, const int32_t* sel, int64_t k, int reset_t)
+template <bool INLINE>
+void launch_write(int nblocks, hipStream_t stream, const float* key, int64_t n, const SelectState* st,
+                  const int32_t* lt, const int32_t* eq, int32_t* sel, const KScene& s, int reset_t)
 {
-    const int lane = threadIdx.x % kWave;
-    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t j = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; j < k; j += waves) {
-        const int32_t i = sel[j];
-        if ((uint64_t)i >= (uint64_t)S.n) continue;
-        for (int gi = 0; gi < S.n_groups; ++gi) {
-            const KGroup& G = S.g[gi];
-            const int64_t base = (int64_t)i * G.dim;
-            for (int c = lane; c < G.dim; c += kWave) {
-                if constexpr (BF16) {
-                    static_cast<uint16_t*>(G.m)[base + c] = 0;
-                    static_cast<uint16_t*>(G.v)[base + c] = 0;
-                } else {
-                    static_cast<float*>(G.m)[base + c] = 0.0f;
-                    static_cast<float*>(G.v)[base + c] = 0.0f;
-                }
-            }
-        }
-        if (reset_t && S.t != nullptr && lane == 0) S.t[i] = 0;
-    }
+    if (s.bf16)
+        hipLaunchKernelGGL((select_write_kernel<INLINE, true>), dim3(nblocks), dim3(kBlock), 0, stream, key, n, st,
+                           lt, eq, sel, s, reset_t);
+    else
+        hipLaunchKernelGGL((select_write_kernel<INLINE, false>), dim3(nblocks), dim3(kBlock), 0, stream, key, n, st,
+                           lt, eq, sel, s, reset_t);
 }
 
 }  // namespace
@@ -289,34 +389,31 @@ __global__ __launch_bounds__(kBlock) void reset_rows_kernel(KScene S, const int3
 size_t relocate_workspace_bytes(int64_t n)
 {
     const size_t nblocks = (size_t)((n + kRelPerBlock - 1) / kRelPerBlock);
-    return kAlign /* states */ + align_up(4 * 256 * 4) /* pass histograms */ + 2 * align_up(nblocks * 4) +
-           align_up((size_t)(n > 0 ? n : 1) * 4) /* selected list when the caller passes none */;
+    return kAlign /* states */ + align_up(kHistWords * 4) /* pass histograms */ +
+           2 * align_up(nblocks * 4) /* per-block counts */;
 }
 
 hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene& s, int reset_t, int32_t* selected,
                            void* ws, hipStream_t stream)
 {
     const int nblocks = (int)((n + kRelPerBlock - 1) / kRelPerBlock);
-    const size_t hist_bytes = align_up(4 * 256 * 4);
+    const size_t hist_bytes = align_up(kHistWords * 4);
     char* p = static_cast<char*>(ws);
     SelectState* st = reinterpret_cast<SelectState*>(p);
     uint32_t* hist = reinterpret_cast<uint32_t*>(p + kAlign);
     int32_t* lt = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes);
     int32_t* eq = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + align_up((size_t)nblocks * 4));
-    int32_t* sel_ws = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + 2 * align_up((size_t)nblocks * 4));
-    int32_t* sel = selected != nullptr ? selected : sel_ws;
 
-    hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, stream, st, hist, (int32_t)k);
+    hipLaunchKernelGGL(select_init_kernel, dim3(4 * kHistCopies), dim3(256), 0, stream, st, hist, (int32_t)k);
     for (int pass = 0; pass < 4; ++pass)
         hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, pass, hist);
     hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, hist, lt, eq);
-    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(kBlock), 0, stream, lt, eq, nblocks);
-    hipLaunchKernelGGL(select_write_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, lt, eq, sel);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || k == 0) return e;
-    const unsigned grid = (unsigned)std::min<int64_t>((k * 64 + kBlock - 1) / kBlock, 4096);
-    if (s.bf16) hipLaunchKernelGGL(reset_rows_kernel<true>, dim3(grid), dim3(kBlock), 0, stream, s, sel, k, reset_t);
-    else hipLaunchKernelGGL(reset_rows_kernel<false>, dim3(grid), dim3(kBlock), 0, stream, s, sel, k, reset_t);
+    if (nblocks <= kInlineScanBlocks) {
+        launch_write<true>(nblocks, stream, key, n, st, lt, eq, selected, s, reset_t);
+    } else {
+        hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(kBlock), 0, stream, lt, eq, nblocks);
+        launch_write<false>(nblocks, stream, key, n, st, lt, eq, selected, s, reset_t);
+    }
     return hipGetLastError();
 }
 

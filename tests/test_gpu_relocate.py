@@ -21,19 +21,20 @@ def _need_gpu():
     oracle.build(force=False)
 
 
-def _run(key: np.ndarray, k: int, bf16: bool = False, reset_t: bool = True, spec=synth.GROUPS_59, seed=0):
+def _run(key: np.ndarray, k: int, bf16: bool = False, reset_t: bool = True, spec=synth.GROUPS_59, seed=0,
+         want_list: bool = True):
     n = key.shape[0]
     st = make_state(gs, n, spec, seed, bf16=bf16)
     before = st.host()
     d_key = torch.from_numpy(key).to(DEV)
     sel = torch.full((max(k, 1),), -7, dtype=torch.int32, device=DEV)
     ws = torch.empty(gs.gs_relocate_workspace_size(n), dtype=torch.uint8, device=DEV)
-    gs.gs_relocate_reset(d_key, k, st.groups, int(bf16), st.t, reset_t, ws, selected=sel)
+    gs.gs_relocate_reset(d_key, k, st.groups, int(bf16), st.t, reset_t, ws, selected=sel if want_list else None)
     torch.cuda.synchronize()
     after = st.host()
     ref = oracle.select_smallest(key, k)
-    got = sel.cpu().numpy()[:k].astype(np.int64)
-    np.testing.assert_array_equal(got, ref)
+    if want_list:
+        np.testing.assert_array_equal(sel.cpu().numpy()[:k].astype(np.int64), ref)
     picked = np.zeros(n, bool)
     picked[ref] = True
     for name, *_ in spec:
@@ -65,6 +66,13 @@ def test_select_continuous_keys_and_signed_zero():
         _run(key, k)
 
 
+def test_reset_without_index_list():
+    """selected = NULL: the rows are still reset, from the same selection."""
+    key = synth.rng(65).integers(-8, 8, 30_001).astype(np.float32)
+    for k in (0, 1, 777, 30_001):
+        _run(key, k, want_list=False, seed=k)
+
+
 def test_bf16_moments_and_keep_t():
     key = synth.rng(62).standard_normal(9000).astype(np.float32)
     _run(key, 90, bf16=True, reset_t=False, spec=synth.GROUPS_60_SPLIT)
@@ -86,3 +94,20 @@ def test_mcmc_shape_6m_one_percent():
     rows = torch.from_numpy(ref).to(DEV)
     assert torch.count_nonzero(st.groups[1].exp_avg[rows]).item() == 0
     assert torch.count_nonzero(st.t[rows]).item() == 0
+
+
+def test_select_past_the_inline_scan_limit():
+    """More than 2048 blocks of 4096 keys: the per-block counts go through
+    the separate scan kernel instead of being summed by each block."""
+    n = 2048 * 4096 + 4097
+    key = (synth.rng(64).integers(-300, 300, n).astype(np.float32) * np.float32(0.5))
+    d_key = torch.from_numpy(key).to(DEV)
+    st = make_state(gs, n, [("opacity", 1, 5e-2, 1)], 6)
+    ws = torch.empty(gs.gs_relocate_workspace_size(n), dtype=torch.uint8, device=DEV)
+    for k in (1, 100_003, n - 5):
+        sel = torch.empty(k, dtype=torch.int32, device=DEV)
+        print(f"relocate n={n} k={k}", flush=True)
+        gs.gs_relocate_reset(d_key, k, st.groups, 0, st.t, True, ws, selected=sel)
+        torch.cuda.synchronize()
+        ref = np.sort(np.argsort(key, kind="stable")[:k])
+        np.testing.assert_array_equal(sel.cpu().numpy().astype(np.int64), ref)
