@@ -26,7 +26,9 @@ The metric is attribute updates per second (visible primitives x 59 per step
 / wall time of the steps).  The JSON line also carries the roofline of the
 dominant kernel measured with HIP events on the launch stream, the FP64
 oracle timed on the host over a bounded sample of the same workload, and the
-other layouts / moment precisions measured the same way ("variants").
+other layouts / moment precisions measured the same way ("variants"), and
+the streaming ceilings of plain contiguous kernels on the same device
+("stream_ceiling": the step's 4-read / 3-write mix, a copy and a read).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--path view|two_launch]
        [--order morton|index] [--moments f32|bf16] [--no-variants] [--no-cpu-baseline]
@@ -185,6 +187,49 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
                       "copy_GBps_rw": 2 * nbytes / dt / 1e9}), flush=True)
     return 0
+
+
+def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
+    """Bandwidth of plain contiguous kernels on this device (libgsprobe):
+    the step's 4-read / 3-write mix over four arrays of `nbytes`, a copy and
+    a read, each timed with HIP events over `reps` launches after 3 untimed
+    ones.  Four arrays of 256 MiB exceed the 256 MB Infinity Cache, so every
+    pass streams from HBM."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2601_16736_amd", "libgsprobe.so"))
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.gsprobe_rmw_4r3w.argtypes = [vp, vp, vp, vp, i64, vp]
+    lib.gsprobe_copy.argtypes = [vp, vp, i64, vp]
+    lib.gsprobe_read.argtypes = [vp, i64, vp, vp]
+    dev = torch.device("cuda:0")
+    arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
+    sink = torch.zeros(4, device=dev)
+    n16 = nbytes // 16
+    stream = torch.cuda.current_stream()
+    sp = vp(stream.cuda_stream)
+    ptr = [a.data_ptr() for a in arrs]
+    calls = {
+        "rmw_4r3w": (lambda: lib.gsprobe_rmw_4r3w(ptr[0], ptr[1], ptr[2], ptr[3], n16, sp), 7 * nbytes),
+        "copy": (lambda: lib.gsprobe_copy(ptr[0], ptr[1], n16, sp), 2 * nbytes),
+        "read": (lambda: lib.gsprobe_read(ptr[0], n16, sink.data_ptr(), sp), nbytes),
+    }
+    out = {}
+    for name, (fn, moved) in calls.items():
+        ev = TimingEvents(reps)
+        for _ in range(3):
+            if fn() != 0:
+                raise RuntimeError(f"gsprobe {name} failed")
+        for j in range(reps):
+            ev.record("start", j, stream)
+            fn()
+            ev.record("end", j, stream)
+        torch.cuda.synchronize()
+        sec = float(np.mean([ev.ms(j) for j in range(reps)])) * 1e-3
+        ev.close()
+        out[f"{name}_GBps"] = moved / sec / 1e9
+    del arrs, sink
+    torch.cuda.empty_cache()
+    return out
 
 
 class SceneOnDevice:
@@ -659,6 +704,12 @@ def main(argv=None) -> int:
         "cpu_baseline": None,
         "variants": variants,
     }
+    print("bench: streaming ceilings", file=sys.stderr, flush=True)
+    ceil = stream_ceilings(torch)
+    ceil["step_frac_of_rmw_4r3w"] = head["achieved_GBps"] / ceil["rmw_4r3w_GBps"]
+    ceil["kind"] = ("plain contiguous kernels, 16-byte non-temporal accesses, 4 in flight per thread, "
+                    "4 x 256 MiB arrays (libgsprobe)")
+    out["stream_ceiling"] = ceil
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams, order, budget_s=args.cpu_budget)

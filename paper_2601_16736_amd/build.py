@@ -1,4 +1,5 @@
-"""Builds libgsopt.so (the gfx950 HIP library) next to this file with hipcc."""
+"""Builds libgsopt.so (the gfx950 HIP library) next to this file with hipcc,
+and libgsprobe.so, the benchmark's streaming-ceiling kernels (probe/)."""
 from __future__ import annotations
 
 import glob
@@ -10,6 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsopt.so")
+PROBE_SRC = os.path.join(HERE, "probe", "stream_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libgsprobe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -27,14 +30,20 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every .hip source into one shared library (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *sources()]
+def _compile(out: str, srcs, verbose: bool) -> None:
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every csrc/.hip source into one shared library, and the probe
+    into its own (always rebuilds both)."""
+    _compile(LIB, sources(), verbose)
+    _compile(PROBE_LIB, [PROBE_SRC], verbose)
     return LIB
 
 
