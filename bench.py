@@ -232,6 +232,19 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
     return out
 
 
+def gpu_clocks():
+    """Current GPU clocks as rocm-smi reports them (the run does not pin
+    them), or None if rocm-smi is not available."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        d = json.loads(r.stdout)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        return None
+    card = next(iter(d.values()), {}) if isinstance(d, dict) else {}
+    return {k: v for k, v in card.items() if "clock" in k.lower()} or None
+
+
 class SceneOnDevice:
     """The scene's attributes and gradient sets in HBM, in a chosen order."""
 
@@ -339,8 +352,104 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
         "visible_mean": float(nv.mean()),
         "achieved_GBps": achieved,
         "step_kernel_us": float(durs[plain].mean() * 1e6) if plain.any() else float("nan"),
+        "step_kernel_us_p10_p50_p90": ([float(x) for x in np.percentile(durs[plain] * 1e6, [10, 50, 90])]
+                                       if plain.any() else None),
         "counts": all_counts,
     }
+
+
+def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, warmup: int = 5):
+    """What fusion buys: the same AdamW-GS step written as one-op-per-pass
+    PyTorch eager kernels over the compacted visible rows.  The library's
+    gs_visibility gives the index list; its count is read to the host, as an
+    eager implementation must, to size the gathers.  Per group: gather the
+    theta, g, m and v rows; moment updates, bias correction, Adam direction,
+    DAR term and parameter update one op at a time; scatter theta, m and v
+    back.  Re-State iterations rescale m and v of a Bernoulli sample drawn
+    with torch's generator.  FP32 moments.  A comparator, not part of the
+    library: before it is timed, three steps of it are checked against the
+    fused step from the same state."""
+    import synth
+    dev = torch.device("cuda:0")
+    b1, b2, eps = 0.9, 0.999, 1e-15
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+
+    def fresh():
+        out = []
+        for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads):
+            lam = LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0)
+            out.append(gs.Group(p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                                dar_lambda=lam, dar_clip=CLIP))
+        return out, torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+
+    def eager_step(groups, t, k):
+        for G, sets in zip(groups, sd.grads):
+            G.grad = sets[k % N_GRAD_SETS]
+        gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt)
+        if k % RSR_EVERY == 0:
+            picked = torch.nonzero(torch.rand(N_PRIMS, generator=gen, device=dev) < RSR_P).squeeze(1)
+            for G in groups:
+                G.exp_avg[picked] = G.exp_avg[picked] * RSR_A1
+                G.exp_avg_sq[picked] = G.exp_avg_sq[picked] * RSR_A2
+        rows = idx[:int(cnt.item())].long()
+        tv = t[rows] + 1
+        t[rows] = tv
+        tf = tv.to(torch.float32)
+        bc1 = (1.0 - torch.pow(b1, tf)).unsqueeze(1)
+        bc2 = (1.0 - torch.pow(b2, tf)).unsqueeze(1)
+        for G in groups:
+            th, g = G.param[rows], G.grad[rows]
+            m, v = G.exp_avg[rows], G.exp_avg_sq[rows]
+            m.mul_(b1).add_(g, alpha=1.0 - b1)
+            v.mul_(b2).addcmul_(g, g, value=1.0 - b2)
+            d = (v / bc2).sqrt_().add_(eps)
+            u = (m / bc1) / d
+            if G.dar_kind == 1:
+                e = torch.exp(-th.abs())
+                u += torch.clamp(G.dar_lambda / REG_NORM * (e / ((1.0 + e) * (1.0 + e))) / d, max=G.dar_clip)
+            elif G.dar_kind == 2:
+                u += torch.clamp(G.dar_lambda / REG_NORM * torch.exp(th) / d, max=G.dar_clip)
+            G.param[rows] = th - G.lr * u
+            G.exp_avg[rows] = m
+            G.exp_avg_sq[rows] = v
+
+    # the comparator computes the same step: three steps from the same state
+    ref, t_ref = fresh()
+    mine, t_mine = fresh()
+    for k in (1, 2, 3):
+        for G, sets in zip(ref, sd.grads):
+            G.grad = sets[k % N_GRAD_SETS]
+        gs.gs_visibility(ref[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt)
+        gs.adamw_gs_step(ref, N_PRIMS, t_ref, gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, **STEP_LAUNCH),
+                         visible=mask, vis_idx=idx, vis_count=cnt)
+        eager_step(mine, t_mine, k)
+    torch.cuda.synchronize()
+    worst = max(float(((A.param - B.param).abs() / B.param.abs().clamp(min=1.0)).max()) for A, B in zip(mine, ref))
+    if not torch.equal(t_mine, t_ref) or worst > 1e-5:
+        raise RuntimeError(f"the unfused comparator does not reproduce the fused step (max err {worst:.3g})")
+    del ref, t_ref, mine, t_mine
+
+    groups, t = fresh()
+    total = warmup + steps
+    for k in range(warmup):
+        eager_step(groups, t, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nv = 0
+    for k in range(warmup, total):
+        eager_step(groups, t, k)
+        nv += int(cnt.item())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del groups, t
+    torch.cuda.empty_cache()
+    return {"path": "unfused eager PyTorch (gs_visibility + one op per pass)", "value": nv * 59 / wall,
+            "ms_per_step": wall / steps * 1e3, "steps": steps, "check_max_err_3_steps": worst}
 
 
 def same_state(torch, a, b) -> bool:
@@ -569,6 +678,8 @@ def main(argv=None) -> int:
                     help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="only run the 6M MCMC-shaped workload with relocation (for profiling)")
+    ap.add_argument("--unfused-only", action="store_true",
+                    help="only run the unfused eager comparator on the 3M Morton scene")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 16-scene batched workload (for profiling)")
     args = ap.parse_args(argv)
@@ -585,6 +696,15 @@ def main(argv=None) -> int:
         import synth
         for r in run_mcmc_both(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup):
             print(json.dumps(r), flush=True)
+        return 0
+    if args.unfused_only:
+        import torch
+        import paper_2601_16736_amd as gs
+        import synth
+        scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
+        cams = synth.camera_rig()
+        order = synth.camera_order(len(cams), 200, seed=0)
+        print(json.dumps(run_unfused(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams, order)), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the AdamW-GS step has no cross-GPU exchange to measure "
@@ -653,6 +773,11 @@ def main(argv=None) -> int:
             else:
                 r.pop("state")
             variants.append(r)
+        print("bench: variant unfused eager comparator", file=sys.stderr, flush=True)
+        unf = run_unfused(gs, torch, layouts["morton"], cams, order)
+        fused_ms = head["ms_per_step"] if (args.order, args.moments) == ("morton", "f32") else None
+        unf["fused_speedup"] = unf["ms_per_step"] / fused_ms if fused_ms else None
+        variants.append({"unfused_comparator": unf})
         del layouts
         torch.cuda.empty_cache()
         print("bench: variant batched 16 scenes", file=sys.stderr, flush=True)
@@ -662,6 +787,7 @@ def main(argv=None) -> int:
         variants.append({"mcmc_6m": view})
         variants.append({"mcmc_6m_two_launch": two})
 
+    traffic = measured_traffic(args.order, args.moments, args.path)
     out = {
         "metric": "primitive-attr updates/s + % HBM roofline, fused AdamW-GS vs plain, 3M Gaussians",
         "value": head["value"],
@@ -696,8 +822,11 @@ def main(argv=None) -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["achieved_GBps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.order, args.moments, args.path),
+            "traffic": traffic,
+            "traffic_GBps": traffic / (head["step_kernel_us"] * 1e3) if traffic else None,
+            "traffic_frac": traffic / (head["step_kernel_us"] * 1e3) / HBM_PEAK_GBS if traffic else None,
             "step_kernel_us": head["step_kernel_us"],
+            "step_kernel_us_p10_p50_p90": head["step_kernel_us_p10_p50_p90"],
             "bytes_per_visible": BYTES_PER_VISIBLE[args.moments],
             "bytes_per_primitive": BYTES_PER_PRIMITIVE[args.path],
         },
@@ -710,6 +839,7 @@ def main(argv=None) -> int:
     ceil["kind"] = ("plain contiguous kernels, 16-byte non-temporal accesses, 4 in flight per thread, "
                     "4 x 256 MiB arrays (libgsprobe)")
     out["stream_ceiling"] = ceil
+    out["gpu_clocks"] = gpu_clocks()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams, order, budget_s=args.cpu_budget)
