@@ -237,8 +237,9 @@ double gs_reg_norm(double n_pixels);
  * BF16 moments are computed in FP32 and rounded once on store, to
  * nearest-even or stochastically: 16 random bits are added below the kept
  * bits, then truncated.  The bits of element e = row*dim+col of group g come
- * from output (e+1) of the stream keyed by (seed, tag 16+g, iteration):
- * bits 63..48 for m, 47..32 for v.  A sampled visible row is rescaled inside
+ * from output (floor(e/2)+1) of the stream keyed by (seed, tag 16+g,
+ * iteration): for even e bits 63..48 for m and 47..32 for v, for odd e bits
+ * 31..16 for m and 15..0 for v.  A sampled visible row is rescaled inside
  * the step (in FP32, before its moment update, no extra rounding); a sampled
  * invisible row is rescaled and rounded with the stream of tag 32+g.
  *

@@ -155,21 +155,39 @@ template <bool BF16, int V> __device__ __forceinline__ void load_moment(const vo
     else load_f<V>(static_cast<const float*>(base) + e, x);
 }
 
-// Stores m and v of V consecutive elements starting at element e.  BF16:
-// element e+q takes its rounding bits from draw (e+q+1) of stream s2.
+// The 32 rounding bits of element e from draw d = output (e/2 + 1) of
+// stream s2: bits 63..32 of d for even e, 31..0 for odd e (m takes the
+// upper 16, v the lower 16), so one draw serves two consecutive elements.
+__device__ __forceinline__ uint32_t sr_word(uint64_t d, int64_t e) { return (e & 1) ? (uint32_t)d : (uint32_t)(d >> 32); }
+
+// Stores m and v of V consecutive elements starting at element e (for V > 1,
+// e is a multiple of V: vector access needs dim % V == 0).  BF16 with
+// stochastic rounding takes the bits of sr_word.
 template <bool BF16, int V>
 __device__ __forceinline__ void store_moments(void* mb, void* vb, int64_t e, const float* m, const float* v,
                                               bool sr, uint64_t s2)
 {
     if constexpr (BF16) {
         uint32_t hm[V], hv[V];
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-            if (sr) {
-                const uint64_t r = d_splitmix(s2, (uint64_t)(e + q) + 1);
-                hm[q] = f32_to_bf16_sr(m[q], (uint32_t)(r >> 48));
-                hv[q] = f32_to_bf16_sr(v[q], (uint32_t)(r >> 32) & 0xFFFFu);
+        if (sr) {
+            if constexpr (V == 1) {
+                const uint32_t w = sr_word(d_splitmix(s2, (uint64_t)(e >> 1) + 1), e);
+                hm[0] = f32_to_bf16_sr(m[0], w >> 16);
+                hv[0] = f32_to_bf16_sr(v[0], w & 0xFFFFu);
             } else {
+#pragma unroll
+                for (int q = 0; q < V; q += 2) {
+                    const uint64_t d = d_splitmix(s2, (uint64_t)((e + q) >> 1) + 1);
+                    const uint32_t hi = (uint32_t)(d >> 32), lo = (uint32_t)d;
+                    hm[q] = f32_to_bf16_sr(m[q], hi >> 16);
+                    hv[q] = f32_to_bf16_sr(v[q], hi & 0xFFFFu);
+                    hm[q + 1] = f32_to_bf16_sr(m[q + 1], lo >> 16);
+                    hv[q + 1] = f32_to_bf16_sr(v[q + 1], lo & 0xFFFFu);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
                 hm[q] = f32_to_bf16_rne(m[q]);
                 hv[q] = f32_to_bf16_rne(v[q]);
             }

@@ -86,7 +86,7 @@ def _run(scene, mode):
     for (name, *_), G, O in zip(spec, groups, og):
         x = G.param[rows_t].cpu().numpy().astype(np.float64)
         e = np.abs(x - O.param) / np.maximum(np.abs(O.param), 1.0)
-        report[name] = {"max": float(e.max()), "mean": float(e.mean())}
+        report[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "mean": float(e.mean())}
     return report
 
 
@@ -111,7 +111,15 @@ def test_moment_precision_drift_1000_steps(scene):
         assert r["max"] <= k_max * 2.0 ** -23, f"FP32 drift of {name}: {r} (bound {k_max * 2.0 ** -23:.2e})"
         assert r["mean"] <= 1e-6, f"FP32 mean drift of {name}: {r}"
     # stochastic rounding wins back the drift that nearest-even storage of the
-    # moments accumulates (small increments to v vanish under nearest-even)
+    # moments accumulates (small increments to v vanish under nearest-even).
+    # The BF16-SR drift of a primitive is a random walk driven by its rounding
+    # draws, so its maximum over the sample is an extreme value that moves
+    # with the draws: over 15 seeds and two assignments of draws to elements
+    # it ranged 0.046-0.109, while the 99.9th percentile stayed in
+    # 0.027-0.029.  The percentile carries the tight bound, the maximum a
+    # guard against gross errors.
     for name in rep["bf16_sr"]:
-        assert rep["bf16_sr"][name]["mean"] < rep["bf16_rne"][name]["mean"], name
-        assert rep["bf16_sr"][name]["max"] <= 0.1, f"bf16_sr drift of {name}: {rep['bf16_sr'][name]}"
+        sr, rne = rep["bf16_sr"][name], rep["bf16_rne"][name]
+        assert sr["mean"] < rne["mean"], name
+        assert sr["p999"] <= 0.04, f"bf16_sr drift of {name}: {sr}"
+        assert sr["max"] <= 0.15, f"bf16_sr drift of {name}: {sr}"
