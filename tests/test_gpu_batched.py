@@ -140,3 +140,100 @@ def test_batch_rejects_bad_plans():
     with pytest.raises(gs.GsError):
         b.step(gs.StepConfig(moment_dtype=gs.GS_MOMENT_BF16))
     b.close()
+
+
+def test_batched_full_size_16_scenes():
+    """The benchmark's many-scene workload at full size: 16 scenes with sizes
+    log-uniform in [2e5, 4e6] (16.3M primitives in all) and Bernoulli
+    visibility U[0.02, 0.60], schedules from the tuner, BF16 moments with
+    stochastic rounding, RSR on.  One plan step equals the 16 per-scene calls
+    bit for bit over every primitive, and sampled visible, invisible and
+    RSR-sampled rows of three scenes match the oracle one by one."""
+    spec = synth.GROUPS_59
+    dims = [d for _, d, _, _ in spec]
+    sizes, ratios = synth.batch_scene_sizes(16, seed=0)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(21)
+    bf = torch.bfloat16
+
+    def rand_state(n):
+        groups = []
+        for name, d, lr, dar in spec:
+            p = torch.randn((n, d), generator=gen, device=DEV)
+            g = torch.randn((n, d), generator=gen, device=DEV) * 1e-3
+            m = (torch.randn((n, d), generator=gen, device=DEV) * 1e-4).to(bf)
+            v = (torch.rand((n, d), generator=gen, device=DEV) * 1e-6 + 1e-9).to(bf)
+            groups.append(gs.Group(p, g, m, v, lr, dar_kind=dar, dar_lambda=1e-3 if dar == 1 else (1e-5 if dar else 0.0),
+                                   dar_clip=10.0))
+        t = torch.randint(0, 40, (n,), generator=gen, device=DEV, dtype=torch.int32)
+        return groups, t
+
+    scenes, refs, masks, scheds = [], [], [], []
+    for s, (n, p) in enumerate(zip(sizes.tolist(), ratios.tolist())):
+        sched, _ = gs.gs_tune(n, dims, float(p), gs.GS_MOMENT_BF16)
+        groups, t = rand_state(n)
+        mask = (torch.rand(n, generator=gen, device=DEV) < p).to(torch.uint8)
+        idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+        if sched == gs.GS_SCHED_COMPACTED:
+            gs.gs_compact(mask, idx, cnt)
+        ref_groups = [gs.Group(g.param.clone(), g.grad, g.exp_avg.clone(), g.exp_avg_sq.clone(), g.lr,
+                               dar_kind=g.dar_kind, dar_lambda=g.dar_lambda, dar_clip=g.dar_clip) for g in groups]
+        scenes.append(gs.Scene(groups=groups, n=n, step_count=t, visible=mask, vis_idx=idx, vis_count=cnt,
+                               schedule=sched, visible_hint=float(p)))
+        refs.append((ref_groups, t.clone()))
+        masks.append(mask)
+        scheds.append(sched)
+    print(f"batched full size: {int(sizes.sum())} primitives, schedules {scheds}", flush=True)
+    cfg = gs.StepConfig(iteration=300, seed=0, rsr_enable=True, rsr_ratio=0.05, moment_dtype=gs.GS_MOMENT_BF16,
+                        stochastic_round=True)
+
+    # sampled rows of three scenes, taken before the step
+    check = [int(np.argmin(sizes)), int(np.argmax(sizes)), 7]
+    r = synth.rng(22)
+    picked, before = {}, {}
+    for s in check:
+        n = int(sizes[s])
+        m = masks[s].cpu().numpy()
+        smp = rsr_sampled_mask(n, cfg.seed + s, cfg.iteration, cfg.rsr_ratio)
+        rows = np.unique(np.concatenate([
+            r.choice(np.flatnonzero(m), min(1500, int(m.sum())), replace=False),
+            r.choice(np.flatnonzero(m == 0), 1500, replace=False),
+            r.choice(np.flatnonzero(smp), 800, replace=False)])).astype(np.int64)
+        picked[s] = (rows, m[rows].copy(), smp[rows])
+        before[s] = _take(scenes[s].groups, scenes[s].step_count, rows, spec)
+
+    batch = gs.Batch(scenes, moment_dtype=gs.GS_MOMENT_BF16)
+    batch.step(cfg)
+    for s, (sc, (rg, rt)) in enumerate(zip(scenes, refs)):
+        gs.adamw_gs_step(rg, sc.n, rt, gs.StepConfig(**dict(vars(cfg), seed=cfg.seed + s, schedule=sc.schedule)),
+                         visible=sc.visible, vis_idx=sc.vis_idx, vis_count=sc.vis_count)
+    torch.cuda.synchronize()
+    for s, (sc, (rg, rt)) in enumerate(zip(scenes, refs)):
+        assert torch.equal(sc.step_count, rt), f"scene {s}: t"
+        for a, b in zip(sc.groups, rg):
+            assert torch.equal(a.param, b.param), f"scene {s}: theta"
+            assert torch.equal(a.exp_avg.view(torch.int16), b.exp_avg.view(torch.int16)), f"scene {s}: m"
+            assert torch.equal(a.exp_avg_sq.view(torch.int16), b.exp_avg_sq.view(torch.int16)), f"scene {s}: v"
+    for s in check:
+        rows, m_rows, smp_rows = picked[s]
+        b = before[s]
+        og = oracle_groups(b, spec, scenes[s].groups)
+        t_ref = b["_t"].copy()
+        ocfg = oracle_config(cfg)
+        ocfg.seed = cfg.seed + s
+        oracle.adamw_gs_step(og, len(rows), m_rows, t_ref, ocfg, ids=rows)
+        after = _take(scenes[s].groups, scenes[s].step_count, rows, spec)
+        compare(after, b, og, spec, t_ref, m_rows.astype(bool) | smp_rows, True, f"full-size scene {s}")
+    batch.close()
+
+
+def _take(groups, t, rows, spec):
+    rows_t = torch.from_numpy(rows).to(DEV)
+    out = {}
+    for (name, *_), g in zip(spec, groups):
+        out[name] = {"param": g.param[rows_t].cpu().numpy(), "grad": g.grad[rows_t].cpu().numpy(),
+                     "m": g.exp_avg[rows_t].float().cpu().numpy().astype(np.float64),
+                     "v": g.exp_avg_sq[rows_t].float().cpu().numpy().astype(np.float64)}
+    out["_t"] = t[rows_t].cpu().numpy()
+    return out
