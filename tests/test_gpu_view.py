@@ -144,23 +144,31 @@ def test_view_step_against_oracle():
     compare(st.host(), before, og, spec, t_ref, touched, False, "view step")
 
 
-def test_view_step_full_size_equals_two_launches():
-    """The benchmark's 3M Morton scene, one step, both paths bit for bit."""
+@pytest.mark.parametrize("bf16", [False, True])
+def test_view_step_full_size_equals_two_launches(bf16):
+    """The benchmark's 3M Morton scene, one step with Re-State, FP32 moments
+    or BF16 with stochastic rounding: both paths bit for bit; the mask equals
+    the oracle's FP32 predicate over all 3M; sampled visible, invisible and
+    Re-State-sampled rows of the fused step match the oracle one by one."""
     import bench
     scene = synth.scene_uniform(bench.N_PRIMS, seed=0)
     sd = bench.SceneOnDevice(gs, torch, scene, "morton")
     n = bench.N_PRIMS
+    spec = synth.GROUPS_59
     cams = synth.camera_rig()
     c = cams[11]
     cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+    mdt = torch.bfloat16 if bf16 else torch.float32
     outs = []
     for fused in (False, True):
-        groups = [gs.Group(p.clone(), sets[1], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+        groups = [gs.Group(p.clone(), sets[1], torch.zeros(p.shape, dtype=mdt, device=DEV),
+                           torch.zeros(p.shape, dtype=mdt, device=DEV), lr, dar_kind=dar,
                            dar_lambda=1e-3 if dar == 1 else (1e-5 if dar == 2 else 0.0), dar_clip=10.0)
-                  for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
+                  for (name, dim, lr, dar), p, sets in zip(spec, sd.params, sd.grads)]
         t = torch.zeros(n, dtype=torch.int32, device=DEV)
         mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
-        cfg = gs.StepConfig(reg_norm=1e5, iteration=100, rsr_enable=True, rsr_ratio=0.05, unit=bench.VIEW_UNIT)
+        cfg = gs.StepConfig(reg_norm=1e5, iteration=100, rsr_enable=True, rsr_ratio=0.05, unit=bench.VIEW_UNIT,
+                            moment_dtype=int(bf16), stochastic_round=bf16)
         if fused:
             gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, cam, visible_out=mask)
         else:
@@ -168,14 +176,40 @@ def test_view_step_full_size_equals_two_launches():
             cfg.schedule, cfg.unit = gs.GS_SCHED_MASKED, 128       # any window gives the same bits
             gs.adamw_gs_step(groups, n, t, cfg, visible=mask)
         torch.cuda.synchronize()
-        outs.append((groups, t, mask))
-    (ga, ta, ma), (gb, tb, mb) = outs
+        outs.append((groups, t, mask, cfg))
+    (ga, ta, ma, _), (gb, tb, mb, cfg) = outs
     assert torch.equal(ma, mb) and torch.equal(ta, tb)
     assert 0.2 < ma.float().mean().item() < 0.4
     for a, b in zip(ga, gb):
         assert torch.equal(a.param, b.param)
-        assert torch.equal(a.exp_avg, b.exp_avg)
-        assert torch.equal(a.exp_avg_sq, b.exp_avg_sq)
+        assert torch.equal(a.exp_avg.view(torch.int16) if bf16 else a.exp_avg,
+                           b.exp_avg.view(torch.int16) if bf16 else b.exp_avg)
+        assert torch.equal(a.exp_avg_sq.view(torch.int16) if bf16 else a.exp_avg_sq,
+                           b.exp_avg_sq.view(torch.int16) if bf16 else b.exp_avg_sq)
+
+    ref_mask = oracle.visibility(sd.params[0].cpu().numpy(), oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width,
+                                                                          c.height, c.z_near, c.z_far))
+    np.testing.assert_array_equal(mb.cpu().numpy(), ref_mask)
+    sampled = oracle.rsr_sample_mask(cfg.seed, cfg.iteration, n, cfg.rsr_ratio)
+    r = synth.rng(41)
+    rows = np.unique(np.concatenate([r.choice(np.flatnonzero(ref_mask), 2000, replace=False),
+                                     r.choice(np.flatnonzero(ref_mask == 0), 2000, replace=False),
+                                     r.choice(np.flatnonzero(sampled), 1000, replace=False)])).astype(np.int64)
+    rows_t = torch.from_numpy(rows).to(DEV)
+    before, after = {}, {}
+    for (name, dim, *_), p, sets, g in zip(spec, sd.params, sd.grads, gb):
+        zero = np.zeros((len(rows), dim))
+        before[name] = {"param": p[rows_t].cpu().numpy(), "grad": sets[1][rows_t].cpu().numpy(), "m": zero,
+                        "v": zero.copy()}
+        after[name] = {"param": g.param[rows_t].cpu().numpy(), "grad": before[name]["grad"],
+                       "m": g.exp_avg[rows_t].float().cpu().numpy().astype(np.float64),
+                       "v": g.exp_avg_sq[rows_t].float().cpu().numpy().astype(np.float64)}
+    before["_t"] = np.zeros(len(rows), np.int32)
+    after["_t"] = tb[rows_t].cpu().numpy()
+    og = oracle_groups(before, spec, gb)
+    t_ref = before["_t"].copy()
+    oracle.adamw_gs_step(og, len(rows), ref_mask[rows].copy(), t_ref, oracle_config(cfg), ids=rows)
+    compare(after, before, og, spec, t_ref, ref_mask[rows].astype(bool) | sampled[rows], bf16, "3M fused step")
 
 
 def test_view_step_rejects_bad_unit_and_camera():
