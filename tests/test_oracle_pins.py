@@ -712,3 +712,43 @@ def test_append_gives_clones_with_a_fresh_state():
         np.testing.assert_allclose(x.param[n:], y.param[n:] - y.lr * gr / (np.abs(gr) + 1e-15), rtol=1e-12,
                                    atol=1e-15)
     assert (t[n:] == 1).all()
+
+
+def test_row_subset_step_equals_the_full_step():
+    """The oracle's step on a subset of a scene's rows (each row keyed by its
+    scene index, as the sampled-row GPU checks use it) must reproduce the
+    pinned full-scene step on those rows exactly: Re-State, AIU and the
+    position-noise draws all follow the scene index, not the row's place in
+    the subset."""
+    n, spec = 600, synth.GROUPS_59
+    rng = np.random.default_rng(23)
+    base = []
+    for name, dim, lr, dar in spec:
+        g = _one_group(n, dim, lr, dar_kind=dar, lam=1e-3, clip=10.0, theta=rng.standard_normal((n, dim)))
+        g.grad[:] = 1e-3 * rng.standard_normal((n, dim))
+        g.m[:] = 1e-4 * rng.standard_normal((n, dim))
+        g.v[:] = 1e-6 * rng.random((n, dim)) + 1e-9
+        base.append(g)
+    t0 = rng.integers(0, 6, n).astype(np.int32)
+    mask = (rng.random(n) < 0.4).astype(np.uint8)
+    cfg = oracle.Config(seed=3, iteration=7, rsr_enable=True, rsr_ratio=0.3, aiu_enable=True, aiu_ratio=0.3,
+                        aiu_scale=0.5, noise_enable=True, noise_groups=(0, 1, 2, 3), noise_lr=20.0)
+    full = [oracle.Group(g.param.copy(), g.grad.copy(), g.m.copy(), g.v.copy(), g.lr, g.dar_kind, g.dar_lambda,
+                         g.dar_clip) for g in base]
+    t_full = t0.copy()
+    oracle.adamw_gs_step(full, n, mask, t_full, cfg)
+    rows = np.sort(rng.choice(n, 151, replace=False)).astype(np.int64)
+    sub = [oracle.Group(g.param[rows].copy(), g.grad[rows].copy(), g.m[rows].copy(), g.v[rows].copy(), g.lr,
+                        g.dar_kind, g.dar_lambda, g.dar_clip) for g in base]
+    t_sub = t0[rows].copy()
+    oracle.adamw_gs_step(sub, len(rows), mask[rows].copy(), t_sub, cfg, ids=rows)
+    np.testing.assert_array_equal(t_sub, t_full[rows])
+    for S, F in zip(sub, full):
+        np.testing.assert_array_equal(S.param, F.param[rows])
+        np.testing.assert_array_equal(S.m, F.m[rows])
+        np.testing.assert_array_equal(S.v, F.v[rows])
+    # the case is not vacuous: visible, Re-State-only and AIU-only rows are all in the subset
+    inv = mask[rows] == 0
+    moved_inv = np.any(sub[4].param[inv] != base[4].param[rows][inv], axis=1)
+    rescaled_inv = np.any(sub[4].m[inv] != base[4].m[rows][inv], axis=1)
+    assert moved_inv.any() and rescaled_inv.any() and (mask[rows] == 1).any()
