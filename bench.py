@@ -470,7 +470,8 @@ def same_state(torch, a, b) -> bool:
         and torch.equal(bits(x.exp_avg_sq), bits(y.exp_avg_sq)) for x, y in zip(ga, gb))
 
 
-def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8):
+def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
+                forms=("batched_bf16", "batched_bf16_resident", "per_scene_bf16", "per_scene_f32")):
     """Many-scene workload: 16 scenes with sizes log-uniform in [2e5, 4e6] and
     visible ratios U[0.02, 0.60] (Bernoulli visibility, 8 pre-drawn masks per
     scene used in turn), 59 attributes each.  Times three forms of the same
@@ -554,8 +555,9 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8)
                        % (int(sizes.sum()), steps),
            "schedules": {"compacted": sum(sc["sched"] == gs.GS_SCHED_COMPACTED for sc in scenes),
                          "masked": sum(sc["sched"] == gs.GS_SCHED_MASKED for sc in scenes)},
-           "visible_per_step": vis_total / steps}
-    for form in ("batched_bf16", "batched_bf16_resident", "per_scene_bf16", "per_scene_f32"):
+           "visible_per_step": vis_total / steps,
+           "algorithmic_bytes_per_step_bf16": vis_total / steps * BYTES_PER_VISIBLE["bf16"] + int(sizes.sum())}
+    for form in forms:
         wall = timed(form)
         out[form] = {"value": vis_total * 59 / wall, "ms_per_step": wall / steps * 1e3}
     scenes.clear()
@@ -690,13 +692,18 @@ def main(argv=None) -> int:
                     help="only run the unfused eager comparator on the 3M Morton scene")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 16-scene batched workload (for profiling)")
+    ap.add_argument("--batched-steps", type=int, default=300,
+                    help="timed steps of the batched workload (default 300)")
+    ap.add_argument("--batched-forms", default="batched_bf16,batched_bf16_resident,per_scene_bf16,per_scene_f32",
+                    help="comma-separated forms of the batched workload to time")
     args = ap.parse_args(argv)
     if args.calibrate_copy:
         return calibrate_copy()
     if args.batched_only:
         import torch
         import paper_2601_16736_amd as gs
-        print(json.dumps(run_batched(gs, torch)), flush=True)
+        print(json.dumps(run_batched(gs, torch, steps=args.batched_steps,
+                                     forms=tuple(args.batched_forms.split(",")))), flush=True)
         return 0
     if args.mcmc_only:
         import torch
