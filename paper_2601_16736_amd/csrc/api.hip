@@ -3,10 +3,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
 #include "internal.h"
+#include "trace.h"
 #include "tuner.h"
 
 namespace gs {
@@ -36,6 +38,23 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 bool finite_d(double x) { return std::isfinite(x); }
 
 }  // namespace
+
+bool trace_on()
+{
+    const char* v = getenv("GSOPT_TRACE");
+    return v != nullptr && v[0] != '\0' && strcmp(v, "0") != 0;
+}
+
+void trace_step(const char* entry, int64_t n, int n_groups, const char* schedule, int unit,
+                const gs_step_config* cfg, const char* detail)
+{
+    if (!trace_on()) return;
+    fprintf(stderr, "gsopt: %s n=%lld groups=%d schedule=%s unit=%d moments=%s iteration=%lld rsr=%d aiu=%d noise=%d%s%s\n",
+            entry, (long long)n, n_groups, schedule, unit,
+            cfg->moment_dtype == GS_MOMENT_BF16 ? (cfg->stochastic_round ? "bf16-sr" : "bf16-rne") : "f32",
+            (long long)cfg->iteration, cfg->rsr_enable, cfg->aiu_enable, cfg->noise_enable, detail[0] ? " " : "",
+            detail);
+}
 
 uint64_t splitmix_output(uint64_t s, uint64_t k)
 {
@@ -375,6 +394,8 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     s.idx = vis_idx;
     s.count = vis_count;
     s.t = step_count;
+    trace_step("adamw_gs_step", n, n_groups,
+               sched == kSchedCompacted ? "compacted" : sched == kSchedMasked ? "masked" : "dense", unit, cfg, "");
     const hipError_t e = launch_step(s, h, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step launch");
 }
@@ -415,6 +436,11 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     s.sched = kSchedMasked;
     s.unit = unit;
     s.t = step_count;
+    if (trace_on()) {
+        char detail[32];
+        snprintf(detail, sizeof detail, "views=%d", n_cams);
+        trace_step("adamw_gs_step_view", n, n_groups, "view", unit, cfg, detail);
+    }
     const hipError_t e = launch_step_view(s, h, k, means, radius, visible_out, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step_view launch");
 }

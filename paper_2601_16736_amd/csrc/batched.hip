@@ -13,10 +13,12 @@
 // HIP graph with one kernel node whose arguments (the step's scalars and the
 // grid, which grows on Re-State iterations) are replaced before each replay.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
 #include "device_common.h"
+#include "trace.h"
 
 namespace gs {
 
@@ -302,6 +304,14 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     b->kh = h;
     b->kb.inv = (h.rsr_thr > 0 || h.aiu_thr > 0) ? 1 : 0;
     const int64_t units = (int64_t)b->kb.step_first[b->n_scenes] + (b->kb.inv ? b->kb.inv_first[b->n_scenes] : 0);
+    if (trace_on()) {
+        int64_t n_all = 0;
+        for (const KScene& K : b->h_scenes) n_all += K.n;
+        char detail[64];
+        snprintf(detail, sizeof detail, "scenes=%d waves=%lld", b->n_scenes, (long long)units);
+        trace_step("adamw_gs_step_batched", n_all, b->h_scenes.empty() ? 0 : b->h_scenes[0].n_groups,
+                   b->persistent_blocks > 0 ? "plan-resident" : "plan", 0, cfg, detail);
+    }
     if (units == 0) {
         const hipError_t e = hipEventRecord(b->done, stream);
         return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
