@@ -56,6 +56,16 @@ void trace_step(const char* entry, int64_t n, int n_groups, const char* schedule
             detail);
 }
 
+int fit_unit(int64_t rows, int unit, int max_unit)
+{
+    while (unit < max_unit) {
+        const int64_t units = (rows + unit - 1) / unit;
+        if ((units + kWavesPerBlock - 1) / kWavesPerBlock <= kMaxGridBlocks) break;
+        unit *= 2;
+    }
+    return unit;
+}
+
 uint64_t splitmix_output(uint64_t s, uint64_t k)
 {
     uint64_t z = s + k * kGamma;
@@ -388,6 +398,7 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     if (st != GS_OK) return st;
     if (n > 0 && (h.rsr_thr > 0 || h.aiu_thr > 0) && sched != kSchedDense && visible == nullptr)
         return fail(GS_EINVAL, "RSR or AIU with a sparse schedule needs the visibility mask (to find invisible rows)");
+    if (sched != kSchedDense) unit = fit_unit(n, unit, 512);
     s.sched = sched;
     s.unit = unit;
     s.mask = visible;
@@ -434,12 +445,12 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     if (unit != 32 && unit != 64 && unit != 128 && unit != 256)
         return fail(GS_EINVAL, "unit = %d: the view step takes 32, 64, 128 or 256 primitives per wave", cfg->unit);
     s.sched = kSchedMasked;
-    s.unit = unit;
+    s.unit = fit_unit(n, unit, 256);
     s.t = step_count;
     if (trace_on()) {
         char detail[32];
         snprintf(detail, sizeof detail, "views=%d", n_cams);
-        trace_step("adamw_gs_step_view", n, n_groups, "view", unit, cfg, detail);
+        trace_step("adamw_gs_step_view", n, n_groups, "view", s.unit, cfg, detail);
     }
     const hipError_t e = launch_step_view(s, h, k, means, radius, visible_out, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step_view launch");

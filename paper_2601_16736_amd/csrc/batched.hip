@@ -321,7 +321,11 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     memset(&p, 0, sizeof p);
     p.func = kernel_for(b->moment_dtype, v);
     const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
-    p.gridDim = dim3((unsigned)(b->persistent_blocks > 0 ? std::min<int64_t>(blocks, b->persistent_blocks) : blocks));
+    // the waves stride over the units, so a grid capped at one dispatch's
+    // limit still covers them all
+    int64_t grid = std::min<int64_t>(blocks, kMaxGridBlocks);
+    if (b->persistent_blocks > 0) grid = std::min<int64_t>(grid, b->persistent_blocks);
+    p.gridDim = dim3((unsigned)grid);
     p.blockDim = dim3(kBlock);
     p.sharedMemBytes = 0;
     p.kernelParams = args;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "trace.h"
 #include "tuner.h"
 
 namespace gs {
@@ -159,6 +160,7 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
     const int reps = 5;
     for (const Cand& c : cands) {
         if (e != hipSuccess) break;
+        if (fit_unit(n, c.unit, c.unit * 2) != c.unit) continue;      // its grid would not fit one dispatch
         s.sched = c.sched;
         s.unit = c.unit;
         for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(s, h, st);
