@@ -460,6 +460,163 @@ def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, war
             "check_rows_stepped": rows_checked, "check_max_theta_move": moved}
 
 
+# position-noise and AIU settings of the widened-row measurements (the paper
+# defers lambda_mu, lambda_t and eta_{R_o} to the 3DGS-MCMC settings and gives
+# Pro_AIU / eta_AIU only per table; these are those defaults and round values)
+NOISE_KW = dict(noise_enable=True, noise_groups=(0, 1, 2, 3), noise_lr=5e5, noise_k=100.0, noise_t=0.005)
+AIU_RATIO, AIU_SCALE = 0.05, 1.0
+
+
+def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, warmup: int = 10) -> dict:
+    """The widened rows on the 3M Morton scene with FP32 moments, each timed
+    with HIP events on the launch stream and read against its algorithmic
+    bytes:
+    - position noise: the fused view step with the noise term on the means;
+    - AIU every step (Pro_AIU 0.05): the fused view step, whose waves also
+      move their windows' sampled invisible rows with t > 0;
+    - four cameras per step: the fused view step over the union of four views;
+    - eight views' visibility in one pass (gs_visibility_multi);
+    - pruning 10 % of the primitives (gs_prune) and appending 5 % as clones
+      (gs_append).
+    The view steps also write their mask (1 B per primitive, counted), from
+    which the visible counts are read outside the timed region."""
+    import synth
+    dev = torch.device("cuda:0")
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    stream = torch.cuda.current_stream()
+    n = N_PRIMS
+
+    def fresh():
+        groups = [gs.Group(p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                           dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+                  for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
+        return groups, torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def view_steps(extra, n_cams=1, aiu=False):
+        groups, t = fresh()
+        mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+        ev = TimingEvents(steps)
+        vis, aiu_rows = [], []
+        for k in range(warmup + steps):
+            for G, sets in zip(groups, sd.grads):
+                G.grad = sets[k % N_GRAD_SETS]
+            cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
+                                rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, unit=VIEW_UNIT, **extra)
+            view = [gcams[order[(k + 53 * j) % len(order)]] for j in range(n_cams)] if n_cams > 1 \
+                else gcams[order[k]]
+            if aiu and k >= warmup:
+                # expected AIU rows of this step: p x (invisible rows with t > 0), t before the step
+                aiu_t = (t > 0)
+            j = k - warmup
+            if j >= 0:
+                ev.record("start", j, stream)
+            gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, view, visible_out=mask, stream=stream)
+            if j >= 0:
+                ev.record("end", j, stream)
+                vis.append(mask.sum(dtype=torch.int64))
+                if aiu:
+                    aiu_rows.append((aiu_t & (mask == 0)).sum(dtype=torch.int64))
+        torch.cuda.synchronize()
+        d = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+        ev.close()
+        nv = np.array([int(x.item()) for x in vis], np.int64)
+        plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
+        byts = nv * BYTES_PER_VISIBLE["f32"] + n * (BYTES_PER_PRIMITIVE["view"] + 1)
+        if aiu:
+            byts = byts + AIU_RATIO * np.array([int(x.item()) for x in aiu_rows], np.float64) * 948
+        del groups, t, mask
+        torch.cuda.empty_cache()
+        ach = float(byts[plain].sum() / d[plain].sum() / 1e9)
+        return {"step_kernel_us": float(d[plain].mean() * 1e6), "visible_mean": float(nv.mean()),
+                "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS}
+
+    view_steps({})                     # discarded: brings the device to its working clocks
+    out = {"plain_view": view_steps({})}
+    out["position_noise"] = view_steps(dict(NOISE_KW))
+    out["aiu_every_step"] = view_steps(dict(aiu_enable=True, aiu_ratio=AIU_RATIO, aiu_scale=AIU_SCALE), aiu=True)
+    out["aiu_every_step"]["bytes_note"] = "948 B per expected AIU row (p x invisible rows with t > 0) added"
+    out["four_views_union"] = view_steps({}, n_cams=4)
+
+    # eight views' visibility in one pass
+    means = sd.params[0]
+    mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+    bits = torch.zeros(n, dtype=torch.int32, device=dev)
+    idx = torch.zeros(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    views = [gcams[order[53 * j % len(order)]] for j in range(8)]
+    reps = 50
+    ev = TimingEvents(reps)
+    for j in range(reps + 3):
+        if j >= 3:
+            ev.record("start", j - 3, stream)
+        gs.gs_visibility_multi(means, views, mask=mask, view_bits=bits, vis_idx=idx, vis_count=cnt, stream=stream)
+        if j >= 3:
+            ev.record("end", j - 3, stream)
+    torch.cuda.synchronize()
+    us = float(np.mean([ev.ms(j) for j in range(reps)]) * 1e3)
+    ev.close()
+    nu = int(cnt.item())
+    mb = n * (12 + 1 + 4) + nu * 4
+    out["visibility_8_views"] = {"kernel_us": us, "union_visible": nu, "achieved_GBps": mb / us / 1e3,
+                                 "frac": mb / us / 1e3 / HBM_PEAK_GBS,
+                                 "bytes": "12 B means + 1 B mask + 4 B view bits per primitive, 4 B per union index"}
+    del mask, bits, idx, cnt
+
+    # pruning 10 % and appending 5 %, on a state that has taken a few steps
+    src, t = fresh()
+    m0 = torch.zeros(n, dtype=torch.uint8, device=dev)
+    for k in range(3):
+        gs.adamw_gs_step_view(src, n, t, gs.StepConfig(reg_norm=REG_NORM, iteration=k, unit=VIEW_UNIT),
+                              src[0].param, gcams[order[k]], visible_out=m0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(17)
+    keep = (torch.rand(n, generator=gen, device=dev) < 0.9).to(torch.uint8)
+    dst = [gs.Group(torch.empty_like(g.param), None, torch.empty_like(g.exp_avg), torch.empty_like(g.exp_avg_sq), g.lr)
+           for g in src]
+    t_dst = torch.empty_like(t)
+    kept = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(gs.gs_prune_workspace_size(n), dtype=torch.uint8, device=dev)
+    ev = TimingEvents(20)
+    for j in range(23):
+        if j >= 3:
+            ev.record("start", j - 3, stream)
+        gs.gs_prune(keep, src, dst, gs.GS_MOMENT_F32, t, t_dst, kept, ws, stream=stream)
+        if j >= 3:
+            ev.record("end", j - 3, stream)
+    torch.cuda.synchronize()
+    us = float(np.mean([ev.ms(j) for j in range(20)]) * 1e3)
+    ev.close()
+    nk = int(kept.item())
+    mb = nk * (59 * 3 * 8 + 8) + n
+    out["prune_10pct"] = {"kernel_us": us, "kept": nk, "achieved_GBps": mb / us / 1e3, "frac": mb / us / 1e3 / HBM_PEAK_GBS,
+                          "bytes": "per kept row theta, m, v read + written (59 x 3 x 8 B) and t (8 B); 1 B of keep per primitive"}
+    del dst, t_dst, ws
+    k_new = n // 20
+    grown = [gs.Group(torch.cat([g.param, torch.zeros((k_new, g.param.shape[1]), device=dev)]), None,
+                      torch.cat([g.exp_avg, torch.zeros((k_new, g.param.shape[1]), device=dev)]),
+                      torch.cat([g.exp_avg_sq, torch.zeros((k_new, g.param.shape[1]), device=dev)]), g.lr)
+             for g in src]
+    t_grown = torch.cat([t, torch.zeros(k_new, dtype=torch.int32, device=dev)])
+    src_idx = torch.randint(0, n, (k_new,), generator=gen, device=dev, dtype=torch.int32)
+    ev = TimingEvents(20)
+    for j in range(23):
+        if j >= 3:
+            ev.record("start", j - 3, stream)
+        gs.gs_append(grown, gs.GS_MOMENT_F32, n, src_idx, t_grown, stream=stream)
+        if j >= 3:
+            ev.record("end", j - 3, stream)
+    torch.cuda.synchronize()
+    us = float(np.mean([ev.ms(j) for j in range(20)]) * 1e3)
+    ev.close()
+    mb = k_new * 948 + k_new * 4
+    out["append_5pct"] = {"kernel_us": us, "appended": k_new, "achieved_GBps": mb / us / 1e3,
+                          "frac": mb / us / 1e3 / HBM_PEAK_GBS,
+                          "bytes": "per new row theta read + written (59 x 8 B), m and v written (59 x 8 B), t written; 4 B of index"}
+    del src, grown, t, t_grown
+    torch.cuda.empty_cache()
+    return out
+
+
 def same_state(torch, a, b) -> bool:
     """Bit equality of two (groups, step counts) end states."""
     (ga, ta), (gb, tb) = a, b
@@ -690,6 +847,8 @@ def main(argv=None) -> int:
                     help="only run the 6M MCMC-shaped workload with relocation (for profiling)")
     ap.add_argument("--unfused-only", action="store_true",
                     help="only run the unfused eager comparator on the 3M Morton scene")
+    ap.add_argument("--next-only", action="store_true",
+                    help="only run the widened rows (noise, AIU, multi-view, prune/append) on the 3M Morton scene")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 16-scene batched workload (for profiling)")
     ap.add_argument("--batched-steps", type=int, default=300,
@@ -711,6 +870,16 @@ def main(argv=None) -> int:
         import synth
         for r in run_mcmc_both(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup):
             print(json.dumps(r), flush=True)
+        return 0
+    if args.next_only:
+        import torch
+        import paper_2601_16736_amd as gs
+        import synth
+        scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
+        cams = synth.camera_rig()
+        order = synth.camera_order(len(cams), 400, seed=0)
+        print(json.dumps(run_next_rows(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams, order)),
+              flush=True)
         return 0
     if args.unfused_only:
         import torch
@@ -788,6 +957,8 @@ def main(argv=None) -> int:
             else:
                 r.pop("state")
             variants.append(r)
+        print("bench: variant widened rows (noise, AIU, multi-view, prune/append)", file=sys.stderr, flush=True)
+        variants.append({"next_rows": run_next_rows(gs, torch, layouts["morton"], cams, order)})
         print("bench: variant unfused eager comparator", file=sys.stderr, flush=True)
         unf = run_unfused(gs, torch, layouts["morton"], cams, order)
         fused_ms = head["ms_per_step"] if (args.order, args.moments) == ("morton", "f32") else None

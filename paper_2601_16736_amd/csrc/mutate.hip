@@ -137,15 +137,20 @@ __global__ __launch_bounds__(kBlock) void prune_move_kernel(KMut M, int64_t unit
 
 __global__ void set_zero_kernel(int32_t* p) { *p = 0; }
 
-// new rows n + [unit*512, unit*512 + 512): clones of src_idx, state zeroed
+// Rows per wave of the append: densification adds a few percent of the
+// scene at a time, so the waves are kept short for enough of them to fill
+// the device (150 000 new rows make 2 344 waves).
+constexpr int kAppendUnit = 64;
+
+// new rows n + [unit*64, unit*64 + 64): clones of src_idx, state zeroed
 __global__ __launch_bounds__(kBlock) void append_kernel(KMut M)
 {
-    __shared__ int s_row[kWavesPerBlock][kMutUnit];
+    __shared__ int s_row[kWavesPerBlock][kAppendUnit];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t j0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kMutUnit;
+    const int64_t j0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kAppendUnit;
     if (j0 >= M.k) return;
-    const int nrows = (int)min((int64_t)kMutUnit, M.k - j0);
+    const int nrows = (int)min((int64_t)kAppendUnit, M.k - j0);
     for (int j = lane; j < nrows; j += kWave) {
         const int32_t s = M.src_idx[j0 + j];
         s_row[wave][j] = (s >= 0 && s < M.n) ? s : -1;
@@ -308,7 +313,7 @@ extern "C" gs_status gs_append(const gs_group* groups, int32_t n_groups, int32_t
     M.n = n;
     M.k = k;
     M.src_idx = src_idx;
-    const int64_t units = (k + kMutUnit - 1) / kMutUnit;
+    const int64_t units = (k + kAppendUnit - 1) / kAppendUnit;
     const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(append_kernel, dim3(blocks), dim3(kBlock), 0, stream, M);
     const hipError_t e = hipGetLastError();
