@@ -52,7 +52,7 @@ struct KBatch {
 
 template <bool BF16, bool NOISE>
 __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, float* s_rb1,
-                                          float* s_rsb2, int lane)
+                                          float* s_rsb2, float* s_noise, int lane)
 {
     int nrows = 0;
     if (S.sched == kSchedCompacted) {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         wave_sync();
         stage_step_rows(nrows, s_row, s_rb1, s_rsb2, S.t, H, d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
-        step_all_groups<BF16, NOISE, kBatchUnroll>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane);
+        step_all_groups<BF16, NOISE, kBatchUnroll>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane, s_noise);
     }
     wave_sync();   // the next unit reuses this wave's LDS rows
 }
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
     __shared__ int s_row[kWavesPerBlock][kBatchCap];
     __shared__ float s_rb1[kWavesPerBlock][kBatchCap];
     __shared__ float s_rsb2[kWavesPerBlock][kBatchCap];
+    __shared__ float s_noise[kWavesPerBlock][NOISE ? 3 * kBatchCap : 1];   // position-noise displacements
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int64_t steps = B.step_first[B.n_scenes];
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
         if (u < steps) {
             const int s = scene_of(B.step_first, B.n_scenes, u);
             step_unit<BF16, NOISE>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave],
-                                   lane);
+                                   s_noise[wave], lane);
         } else {
             const int64_t v = u - steps;
             const int s = scene_of(B.inv_first, B.n_scenes, v);

@@ -220,15 +220,23 @@ __device__ __forceinline__ float reg_term(int kind, int mode, float scale, float
     return fminf(scale * R, clip);
 }
 
-// Component c of the position-noise displacement eta_{R_o} R_mu of primitive
-// i (definition in gsopt.h): Sigma gamma from the pre-update quaternion and
-// log-scale, gated by the pre-update opacity.  `scale` = eta_{R_o} eta_mu.
-__device__ __forceinline__ float noise_component(const float* qp, const float* kp, const float* tp, int64_t i,
-                                                 int c, uint64_t s2, float scale, float k, float t0)
+struct NoiseArgs {
+    const float* q;      // quaternion group's attributes
+    const float* kappa;  // log-scale group's attributes
+    const float* tau;    // opacity-logit group's attributes
+    uint64_t s2;         // stream (seed, tag 48, iteration)
+    float scale;         // eta_{R_o} * eta_mu
+};
+
+// Position-noise displacement eta_{R_o} R_mu of primitive i (definition in
+// gsopt.h), all three components: Sigma gamma from the pre-update quaternion
+// and log-scale, gated by the pre-update opacity.  `nz.scale` = eta_{R_o}
+// eta_mu.
+__device__ __forceinline__ void noise_row(const NoiseArgs& nz, int64_t i, float k, float t0, float* out)
 {
     // gamma ~ N(0, I3): Box-Muller on 24-bit uniforms of two draws
-    const uint64_t d1 = d_splitmix(s2, 2 * (uint64_t)i + 1);
-    const uint64_t d2 = d_splitmix(s2, 2 * (uint64_t)i + 2);
+    const uint64_t d1 = d_splitmix(nz.s2, 2 * (uint64_t)i + 1);
+    const uint64_t d2 = d_splitmix(nz.s2, 2 * (uint64_t)i + 2);
     const float u1 = (float)((uint32_t)(d1 >> 40) + 1u) * 0x1p-24f;
     const float a1 = (float)((uint32_t)(d1 >> 8) & 0xFFFFFFu) * 0x1p-24f;
     const float u2 = (float)((uint32_t)(d2 >> 40) + 1u) * 0x1p-24f;
@@ -240,6 +248,8 @@ __device__ __forceinline__ float noise_component(const float* qp, const float* k
     sincospif(2.0f * a2, &sn2, &cs2);
     const float g0 = r1 * cs1, g1 = r1 * sn1, g2 = r2 * cs2;
     // rotation of the normalised quaternion (w, x, y, z)
+    const float* qp = nz.q;
+    const float* kp = nz.kappa;
     float w = qp[4 * i], x = qp[4 * i + 1], y = qp[4 * i + 2], z = qp[4 * i + 3];
     const float inv = 1.0f / __fsqrt_rn(w * w + x * x + y * y + z * z);
     w *= inv; x *= inv; y *= inv; z *= inv;
@@ -250,31 +260,23 @@ __device__ __forceinline__ float noise_component(const float* qp, const float* k
     const float e0 = (R00 * g0 + R10 * g1 + R20 * g2) * expf(2.0f * kp[3 * i]);
     const float e1 = (R01 * g0 + R11 * g1 + R21 * g2) * expf(2.0f * kp[3 * i + 1]);
     const float e2 = (R02 * g0 + R12 * g1 + R22 * g2) * expf(2.0f * kp[3 * i + 2]);
-    const float sg = c == 0 ? R00 * e0 + R01 * e1 + R02 * e2
-                   : c == 1 ? R10 * e0 + R11 * e1 + R12 * e2
-                            : R20 * e0 + R21 * e1 + R22 * e2;
-    const float o = 1.0f / (1.0f + expf(-tp[i]));
+    const float o = 1.0f / (1.0f + expf(-nz.tau[i]));
     const float gate = 1.0f / (1.0f + expf(k * (o - t0)));            // sigma(-k (o - t))
-    return scale * gate * sg;
+    out[0] = nz.scale * gate * (R00 * e0 + R01 * e1 + R02 * e2);
+    out[1] = nz.scale * gate * (R10 * e0 + R11 * e1 + R12 * e2);
+    out[2] = nz.scale * gate * (R20 * e0 + R21 * e1 + R22 * e2);
 }
 
-struct NoiseArgs {
-    const float* q;      // quaternion group's attributes
-    const float* kappa;  // log-scale group's attributes
-    const float* tau;    // opacity-logit group's attributes
-    uint64_t s2;         // stream (seed, tag 48, iteration)
-    float scale;         // eta_{R_o} * eta_mu
-};
 
 // One group's read-modify-write pass over the wave's staged rows.  Each
 // lane takes U (row, chunk) items per trip and issues all their loads before
 // any store, so a wave keeps U x 4 vector loads in flight.  NOISE (mean
-// group only, V = 1) subtracts the position-noise displacement after the
-// Adam update.
+// group only, V = 1) subtracts the position-noise displacement, staged per
+// row in s_noise, after the Adam update.
 template <bool BF16, int V, int U, bool NOISE = false>
 __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int nrows,
                                            const int* s_row, const float* s_rb1, const float* s_rsb2,
-                                           int lane, float dar_scale, uint64_t sr_s2, const NoiseArgs* nz = nullptr)
+                                           int lane, float dar_scale, uint64_t sr_s2, const float* s_noise = nullptr)
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
@@ -288,9 +290,11 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
         int64_t e[U];
         float c1[U], c2[U], rb1[U], rsb2[U];
         bool ok[U];
+        int nidx[U];      // NOISE: the item's slot in s_noise
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             ok[u] = k0 + u * kWave < items;
+            nidx[u] = 3 * r + c;
             const int raw = ok[u] ? s_row[r] : 0;
             // a row in this iteration's Re-State sample decays by alpha before
             // the moment update: beta*(alpha*m) folded into (beta*alpha)*m
@@ -329,11 +333,7 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
 #endif
                 if (dar) uu += reg_term(G.dar_kind, G.reg_mode, dar_scale, G.dar_clip, th[u][q], d);
                 th[u][q] = th[u][q] - G.lr * uu;
-                if constexpr (NOISE) {
-                    const int64_t prim = e[u] / 3;          // the mean group has dim 3 (and V = 1)
-                    th[u][q] -= noise_component(nz->q, nz->kappa, nz->tau, prim, (int)(e[u] - prim * 3), nz->s2,
-                                                nz->scale, H.noise_k, H.noise_t);
-                }
+                if constexpr (NOISE) th[u][q] -= s_noise[nidx[u]];     // the mean group: dim 3, V = 1
                 m[u][q] = mm;
                 v[u][q] = vv;
             }
@@ -515,7 +515,7 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
 template <bool BF16, bool NOISE, int U>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
                                                 const int* s_row, const float* s_rb1, const float* s_rsb2,
-                                                int lane)
+                                                int lane, float* s_noise = nullptr)
 {
     // With position noise the mean group goes first, so the quaternion,
     // log-scale and opacity rows it reads are still the pre-update ones.
@@ -536,7 +536,12 @@ __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H
                                     ? (float)(G.dar_lambda / H.reg_norm)
                                     : (float)G.dar_lambda;
         const uint64_t s2 = BF16 ? d_stream(seed, kTagSrStep + (uint64_t)first, H.iteration) : 0;
-        step_group<BF16, 1, 4, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, &nz);
+        // each lane forms whole rows' displacements (3 floats per staged row),
+        // then the mean group's items read their component
+        for (int j = lane; j < nrows; j += kWave)
+            noise_row(nz, (int64_t)(s_row[j] & 0x7FFFFFFF), H.noise_k, H.noise_t, &s_noise[3 * j]);
+        wave_sync();
+        step_group<BF16, 1, U * 2, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, s_noise);
     }
     for (int gi = 0; gi < S.n_groups; ++gi) {
         if (gi == first) continue;

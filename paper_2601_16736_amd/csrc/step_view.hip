@@ -41,6 +41,7 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
     __shared__ int s_row[kWavesPerBlock][UNIT];
     __shared__ float s_rb1[kWavesPerBlock][UNIT];
     __shared__ float s_rsb2[kWavesPerBlock][UNIT];
+    __shared__ float s_noise[kWavesPerBlock][NOISE ? 3 * UNIT : 1];   // position-noise displacements
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * UNIT;
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
                         d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
         step_all_groups<BF16, NOISE, BF16 ? GS_STEP_UNROLL_BF16 : GS_STEP_UNROLL>(S, H, seed, nrows, s_row[wave],
-                                                                                  s_rb1[wave], s_rsb2[wave], lane);
+                                                                                  s_rb1[wave], s_rsb2[wave], lane,
+                                                                                  s_noise[wave]);
     }
     if (H.rsr_thr == 0 && H.aiu_thr == 0) return;
 
