@@ -11,8 +11,12 @@
 
 namespace gs {
 
-constexpr int kVisRounds = 16;
+#ifndef GS_VIS_ROUNDS
+#define GS_VIS_ROUNDS 16
+#endif
+constexpr int kVisRounds = GS_VIS_ROUNDS;
 constexpr int kVisPerBlock = kBlock * kVisRounds;
+static_assert(kVisRounds * kWavesPerBlock <= kWave, "the block's (round, wave) counts fit one wave");
 
 // Appends the visible primitives of this block (flags per round) to idx.
 __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int64_t first, int32_t* idx,
@@ -30,16 +34,15 @@ __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int6
     }
     __syncthreads();
     if (threadIdx.x < kWave) {
-        // exclusive prefix of the 64 (round, wave) counts across wave 0
-        static_assert(kVisRounds * kWavesPerBlock == kWave, "one count per lane of wave 0");
-        const int c = s_cnt[threadIdx.x];
+        // exclusive prefix of the (round, wave) counts across wave 0
+        const int c = threadIdx.x < kVisRounds * kWavesPerBlock ? s_cnt[threadIdx.x] : 0;
         int incl = c;
 #pragma unroll
         for (int off = 1; off < kWave; off <<= 1) {
             const int y = __shfl_up(incl, off);
             if ((int)threadIdx.x >= off) incl += y;
         }
-        s_cnt[threadIdx.x] = incl - c;
+        if (threadIdx.x < kVisRounds * kWavesPerBlock) s_cnt[threadIdx.x] = incl - c;
         const int total = __shfl(incl, kWave - 1);
         if (threadIdx.x == 0) s_base = total > 0 ? atomicAdd(count, total) : 0;
     }
