@@ -175,7 +175,9 @@ typedef struct {
     double rsr_ratio;        /* sampling probability p in [0, 1] */
     float visible_hint;      /* expected visible fraction for GS_SCHED_AUTO (<= 0: unknown) */
     int32_t unit;            /* rows (compacted: 32, 64, 128, 256, 512) / primitives (masked: 32, 64,
-                                128, 256, 512; dense: 64, 256, 512) per wave; 0 = default */
+                                128, 256, 512; dense: 64, 256, 512) per wave; 0 = default.  A scene too
+                                large for one dispatch at this unit (above 2^31 - 128 rows at 32) runs
+                                at the next size, with the same results */
     /* Position noise (Implementation Details, position equations): each
      * visible primitive's mean also moves by -eta_{R_o} R_mu, R_mu =
      * eta_mu sigma(-lambda_mu (sigma(tau) - lambda_t)) Sigma gamma, with
