@@ -30,6 +30,10 @@ def _need_gpu():
     if free < 140 << 30:
         pytest.skip("needs about 140 GB of free device memory")
     oracle.build(force=False)
+    yield
+    # the tests after this module run in the same process
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 def _sample_rows(n, seed):
