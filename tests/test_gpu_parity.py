@@ -409,3 +409,77 @@ def test_full_size_scene_sampled_rows():
     np.testing.assert_array_equal(dt, m.astype(np.int32))
     for s0, g in zip(snap, st.groups[:2]):
         assert torch.equal(g.param[untouched], s0)
+
+
+def _edge_means(n, seed, fx, cx, W, with_radius, f_max=None, r_min=0.0):
+    """Means whose projection by the axis camera (R = I, t = (0, 0, 15)) lands
+    within a few ulps of an image edge (u = 0 or W, v = 0 or H), and radii
+    within a few ulps of r_min: the cases the predicate's fast decision hands
+    to the exact divisions.  Returns (means, radius or None)."""
+    r = synth.rng(seed, 52)
+    pz = r.uniform(0.5, 17.0, n)
+    edge = r.integers(0, 4, n)                       # u = 0, u = W, v = 0, v = H
+    target = np.where(edge % 2 == 0, 0.0, W)
+    # half on the edge (then walked by ulps), half up to 0.2 px to either side:
+    # the fast decision takes the latter, the exact divisions the former
+    target = target + np.where(r.random(n) < 0.5, 0.0, r.uniform(-0.2, 0.2, n))
+    along = (target - cx) * pz / fx                  # coordinate on the edge, float64
+    other = r.uniform(-0.4, 0.4, n) * pz * W / fx    # well inside the other axis
+    mu = np.zeros((n, 3), np.float32)
+    ax = np.where(edge < 2, 0, 1)
+    mu[np.arange(n), ax] = along.astype(np.float32)
+    mu[np.arange(n), 1 - ax] = other.astype(np.float32)
+    mu[:, 2] = (pz - 15.0).astype(np.float32)
+    # walk the edge coordinate by -6 .. +6 ulps
+    steps = r.integers(-6, 7, n)
+    col = mu[np.arange(n), ax]
+    for k in range(1, 7):
+        col = np.where(steps >= k, np.nextafter(col, np.float32(np.inf)), col)
+        col = np.where(steps <= -k, np.nextafter(col, np.float32(-np.inf)), col)
+    mu[np.arange(n), ax] = col.astype(np.float32)
+    rad = None
+    if with_radius:
+        # radii with r = f_max rho / p_z within a few ulps of r_min, or small
+        base = (r_min * (mu[:, 2].astype(np.float64) + 15.0) / f_max).astype(np.float32)
+        rs = r.integers(-4, 5, n)
+        for k in range(1, 5):
+            base = np.where(rs >= k, np.nextafter(base, np.float32(np.inf)), base)
+            base = np.where(rs <= -k, np.nextafter(base, np.float32(-np.inf)), base)
+        rad = np.where(r.random(n) < 0.5, base, (r.random(n) * 0.01).astype(np.float32)).astype(np.float32)
+    return mu, rad
+
+
+@pytest.mark.parametrize("with_radius", [False, True])
+def test_visibility_bit_exact_at_image_edges(with_radius):
+    """Points within a few ulps of the image edges (and radii at r_min): the
+    single-view, multi-view and fused-step masks equal the oracle's FP32
+    predicate exactly."""
+    n = 200_003
+    cams = _cams()
+    axis = synth.CameraSpec(np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 15]], np.float32),
+                            cams[0].fx, cams[0].fy, 500.0, 500.0, 1000, 1000, 0.2, 17.5)
+    kw = {"r_min": 0.5} if with_radius else {}
+    means, radius = _edge_means(n, 5, axis.fx, axis.cx, 1000.0, with_radius, f_max=max(axis.fx, axis.fy),
+                                r_min=0.5)
+    ref = oracle.visibility(means, _ocam(axis, **kw), radius)
+    assert 0.2 < ref.mean() < 0.8
+    d_means = torch.from_numpy(means).to(DEV)
+    d_rad = torch.from_numpy(radius).to(DEV) if with_radius else None
+    mask = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.gs_visibility(d_means, _gcam(axis, **kw), mask=mask, radius=d_rad)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(mask.cpu().numpy(), ref)
+    mask2 = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    bits = torch.zeros(n, dtype=torch.int32, device=DEV)
+    gs.gs_visibility_multi(d_means, [_gcam(cams[3], **kw), _gcam(axis, **kw)], mask=mask2, view_bits=bits,
+                           radius=d_rad)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal((bits.cpu().numpy() >> 1) & 1, ref)
+    # the fused step's cull
+    st = make_state(gs, n, [("means", 3, 1e-3, 0)], 9)
+    st.groups[0].param.copy_(d_means)
+    vis = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(iteration=1), d_means.clone(), _gcam(axis, **kw),
+                          radius=d_rad, visible_out=vis)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(vis.cpu().numpy(), ref)
