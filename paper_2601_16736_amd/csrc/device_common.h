@@ -510,8 +510,8 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
 }
 
 // Every group's pass over the staged rows.  U: (row, chunk) items per lane
-// per trip for the 16/8-byte groups (twice that for 4-byte ones); the noise
-// group, whose items carry the displacement arithmetic, uses 4.
+// per trip for the 16/8-byte groups (twice that for 4-byte ones, the noise
+// group included).
 template <bool BF16, bool NOISE, int U>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
                                                 const int* s_row, const float* s_rb1, const float* s_rsb2,
