@@ -114,8 +114,8 @@ __device__ __forceinline__ void load_keys(const float* __restrict__ key, int64_t
 __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t n,
                                                              SelectState* st, int pass, uint32_t* hist)
 {
-    // one private histogram per wave: the keys of a view are concentrated in
-    // a few digits, and four copies cut the LDS atomic collisions fourfold
+    // one private histogram per wave: keys such as opacity logits fall into
+    // a few top digits, and four copies cut the LDS atomic collisions fourfold
     __shared__ uint32_t s_hist[kWavesPerBlock][256];
     for (int w = 0; w < kWavesPerBlock; ++w) s_hist[w][threadIdx.x] = 0u;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
