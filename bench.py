@@ -617,6 +617,73 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     return out
 
 
+def run_sweep(gs, torch, steps: int = 100, warmup: int = 10) -> list:
+    """The fused view step (FP32, windows of VIEW_UNIT, Morton order) over
+    scene sizes 1M-24M at the rig's z_far 17.5, and over visible fractions
+    (z_far 15, 17.5, 20, 25, infinity) at 3M.  Scenes are drawn on the
+    device (means U[-10, 10]^3, other attributes N(0, 1), one gradient set
+    N(0, 1e-3)).  The step writes its mask, whose counts, read outside the
+    timed region, give the algorithmic bytes (1660 B per visible + 13 B per
+    primitive)."""
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = []
+
+    def one(n, z_far):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(n)
+        means = torch.rand((n, 3), generator=gen, device=dev) * 20.0 - 10.0
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = torch.empty(gs.gs_spatial_order_workspace_size(n), dtype=torch.uint8, device=dev)
+        gs.gs_spatial_order(means, perm, ws)
+        means = gs.apply_spatial_order([means], perm)[0]
+        del perm, ws
+        groups = []
+        for k, (name, d, lr, dar) in enumerate(synth.GROUPS_59):
+            p = means if k == 0 else torch.randn((n, d), generator=gen, device=dev)
+            g = torch.randn((n, d), generator=gen, device=dev) * 1e-3
+            groups.append(gs.Group(p, g, torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                                   dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0),
+                                   dar_clip=CLIP))
+        t = torch.zeros(n, dtype=torch.int32, device=dev)
+        mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+        cams = synth.camera_rig(z_far=z_far)
+        gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+        order = synth.camera_order(len(cams), warmup + steps, seed=1)
+        ev = TimingEvents(steps)
+        vis = []
+        for k in range(warmup + steps):
+            cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k + 1, unit=VIEW_UNIT)
+            j = k - warmup
+            if j >= 0:
+                ev.record("start", j, stream)
+            gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, gcams[order[k]], visible_out=mask,
+                                  stream=stream)
+            if j >= 0:
+                ev.record("end", j, stream)
+                vis.append(mask.sum(dtype=torch.int64))
+        torch.cuda.synchronize()
+        d = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+        ev.close()
+        nv = np.array([int(x.item()) for x in vis], np.int64)
+        byts = nv * BYTES_PER_VISIBLE["f32"] + n * (BYTES_PER_PRIMITIVE["view"] + 1)
+        ach = float(byts.sum() / d.sum() / 1e9)
+        del groups, t, mask, means
+        torch.cuda.empty_cache()
+        return {"n": n, "z_far": z_far, "visible_frac": float(nv.mean() / n), "step_kernel_us": float(d.mean() * 1e6),
+                "attr_updates_per_s": float(nv.sum() * 59 / d.sum()), "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS}
+
+    one(1_000_000, 17.5)                  # discarded: brings the device to its working clocks
+    for n in (1_000_000, 3_000_000, 6_000_000, 12_000_000, 24_000_000):
+        out.append(one(n, 17.5))
+        print(f"bench: sweep n={n} done", file=sys.stderr, flush=True)
+    for z_far in (15.0, 20.0, 25.0, float("inf")):
+        out.append(one(3_000_000, z_far))
+        print(f"bench: sweep z_far={z_far} done", file=sys.stderr, flush=True)
+    return out
+
+
 def same_state(torch, a, b) -> bool:
     """Bit equality of two (groups, step counts) end states."""
     (ga, ta), (gb, tb) = a, b
@@ -847,6 +914,8 @@ def main(argv=None) -> int:
                     help="only run the 6M MCMC-shaped workload with relocation (for profiling)")
     ap.add_argument("--unfused-only", action="store_true",
                     help="only run the unfused eager comparator on the 3M Morton scene")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the fused view step over scene sizes 1M-24M and visible fractions (z_far)")
     ap.add_argument("--next-only", action="store_true",
                     help="only run the widened rows (noise, AIU, multi-view, prune/append) on the 3M Morton scene")
     ap.add_argument("--batched-only", action="store_true",
@@ -869,6 +938,12 @@ def main(argv=None) -> int:
         import paper_2601_16736_amd as gs
         import synth
         for r in run_mcmc_both(gs, torch, synth.camera_rig(), steps=args.steps, warmup=args.warmup):
+            print(json.dumps(r), flush=True)
+        return 0
+    if args.sweep:
+        import torch
+        import paper_2601_16736_amd as gs
+        for r in run_sweep(gs, torch):
             print(json.dumps(r), flush=True)
         return 0
     if args.next_only:
