@@ -1095,10 +1095,13 @@ def main(argv=None) -> int:
         "variants": variants,
     }
     print("bench: streaming ceilings", file=sys.stderr, flush=True)
-    ceil = stream_ceilings(torch)
-    ceil["step_frac_of_rmw_4r3w"] = head["achieved_GBps"] / ceil["rmw_4r3w_GBps"]
-    ceil["kind"] = ("plain contiguous kernels, 16-byte non-temporal accesses, 4 in flight per thread, "
-                    "4 x 256 MiB arrays (libgsprobe)")
+    try:
+        ceil = stream_ceilings(torch)
+        ceil["step_frac_of_rmw_4r3w"] = head["achieved_GBps"] / ceil["rmw_4r3w_GBps"]
+        ceil["kind"] = ("plain contiguous kernels, 16-byte non-temporal accesses, 4 in flight per thread, "
+                        "4 x 256 MiB arrays (libgsprobe)")
+    except OSError as e:                  # the probe library is context, not the measurement
+        ceil = {"error": f"libgsprobe.so not loadable: {e}"}
     out["stream_ceiling"] = ceil
     out["gpu_clocks"] = gpu_clocks()
     if not args.no_cpu_baseline:
