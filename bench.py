@@ -617,7 +617,7 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     return out
 
 
-def run_sweep(gs, torch, steps: int = 100, warmup: int = 10) -> list:
+def run_sweep(gs, torch, steps: int = 100, warmup: int = 10, only_n: int = 0) -> list:
     """The fused view step (FP32, windows of VIEW_UNIT, Morton order) over
     scene sizes 1M-24M at the rig's z_far 17.5, and over visible fractions
     (z_far 15, 17.5, 20, 25, infinity) at 3M.  Scenes are drawn on the
@@ -675,6 +675,8 @@ def run_sweep(gs, torch, steps: int = 100, warmup: int = 10) -> list:
                 "attr_updates_per_s": float(nv.sum() * 59 / d.sum()), "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS}
 
     one(1_000_000, 17.5)                  # discarded: brings the device to its working clocks
+    if only_n > 0:
+        return [one(only_n, 17.5)]
     for n in (1_000_000, 3_000_000, 6_000_000, 12_000_000, 24_000_000):
         out.append(one(n, 17.5))
         print(f"bench: sweep n={n} done", file=sys.stderr, flush=True)
@@ -916,6 +918,8 @@ def main(argv=None) -> int:
                     help="only run the unfused eager comparator on the 3M Morton scene")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the fused view step over scene sizes 1M-24M and visible fractions (z_far)")
+    ap.add_argument("--sweep-n", type=int, default=0,
+                    help="with --sweep: only this scene size (at z_far 17.5), e.g. for a profiled run")
     ap.add_argument("--next-only", action="store_true",
                     help="only run the widened rows (noise, AIU, multi-view, prune/append) on the 3M Morton scene")
     ap.add_argument("--batched-only", action="store_true",
@@ -943,7 +947,7 @@ def main(argv=None) -> int:
     if args.sweep:
         import torch
         import paper_2601_16736_amd as gs
-        for r in run_sweep(gs, torch):
+        for r in run_sweep(gs, torch, only_n=args.sweep_n):
             print(json.dumps(r), flush=True)
         return 0
     if args.next_only:
