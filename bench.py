@@ -471,7 +471,9 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     """The widened rows on the 3M Morton scene with FP32 moments, each timed
     with HIP events on the launch stream and read against its algorithmic
     bytes:
-    - position noise: the fused view step with the noise term on the means;
+    - position noise: the fused view step with the noise term on the means,
+      with the scene's N(0, 1) log-scales and with small ones (N(ln 0.01,
+      0.5), beside the plain step on the same scales);
     - AIU every step (Pro_AIU 0.05): the fused view step, whose waves also
       move their windows' sampled invisible rows with t > 0;
     - four cameras per step: the fused view step over the union of four views;
@@ -492,8 +494,15 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
                   for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
         return groups, torch.zeros(n, dtype=torch.int32, device=dev)
 
-    def view_steps(extra, n_cams=1, aiu=False):
+    def view_steps(extra, n_cams=1, aiu=False, small_scales=False):
         groups, t = fresh()
+        if small_scales:
+            # log-scales ~ N(ln 0.01, 0.5), the size of a trained scene's
+            # Gaussians: the noise displacement stays small, so the means keep
+            # their Morton runs and the time is the noise computation's
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(29)
+            groups[1].param.copy_(torch.randn(groups[1].param.shape, generator=gen, device=dev) * 0.5 - 4.6)
         mask = torch.zeros(n, dtype=torch.uint8, device=dev)
         ev = TimingEvents(steps)
         vis, aiu_rows = [], []
@@ -533,6 +542,8 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     view_steps({})                     # discarded: brings the device to its working clocks
     out = {"plain_view": view_steps({})}
     out["position_noise"] = view_steps(dict(NOISE_KW))
+    out["position_noise_small_scales"] = view_steps(dict(NOISE_KW), small_scales=True)
+    out["plain_view_small_scales"] = view_steps({}, small_scales=True)
     out["aiu_every_step"] = view_steps(dict(aiu_enable=True, aiu_ratio=AIU_RATIO, aiu_scale=AIU_SCALE), aiu=True)
     out["aiu_every_step"]["bytes_note"] = "948 B per expected AIU row (p x invisible rows with t > 0) added"
     out["four_views_union"] = view_steps({}, n_cams=4)
