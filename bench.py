@@ -509,8 +509,9 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
         for k in range(warmup + steps):
             for G, sets in zip(groups, sd.grads):
                 G.grad = sets[k % N_GRAD_SETS]
+            # windows: the library's default (32; 64 with position noise)
             cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
-                                rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, unit=VIEW_UNIT, **extra)
+                                rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **extra)
             view = [gcams[order[(k + 53 * j) % len(order)]] for j in range(n_cams)] if n_cams > 1 \
                 else gcams[order[k]]
             if aiu and k >= warmup:

@@ -175,7 +175,8 @@ typedef struct {
     double rsr_ratio;        /* sampling probability p in [0, 1] */
     float visible_hint;      /* expected visible fraction for GS_SCHED_AUTO (<= 0: unknown) */
     int32_t unit;            /* rows (compacted: 32, 64, 128, 256, 512) / primitives (masked: 32, 64,
-                                128, 256, 512; dense: 64, 256, 512) per wave; 0 = default.  A scene too
+                                128, 256, 512; dense: 64, 256, 512) per wave; 0 = default (compacted 64,
+                                masked 32 or, with position noise, 64; dense 64).  A scene too
                                 large for one dispatch at this unit (above 2^31 - 128 rows at 32) runs
                                 at the next size, with the same results */
     /* Position noise (Implementation Details, position equations): each
@@ -267,7 +268,8 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n,
  * they are when the call starts, then the step above runs with that V.
  * With several cameras (n_cams in 1..32, a host array; a batch of training
  * views) V is their union, as the mask of gs_visibility_multi.  Each wave
- * takes a window of cfg->unit primitives (32, 64, 128 or 256; 0 = 32): it
+ * takes a window of cfg->unit primitives (32, 64, 128 or 256; 0 = 32, or 64
+ * with position noise): it
  * culls the window, steps its visible rows and, when Re-State or AIU is
  * on, treats its invisible sampled rows, so no mask or index list passes
  * through memory in between.  Results equal the visibility call followed
