@@ -269,7 +269,7 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n,
  * With several cameras (n_cams in 1..32, a host array; a batch of training
  * views) V is their union, as the mask of gs_visibility_multi.  Each wave
  * takes a window of cfg->unit primitives (32, 64, 128 or 256; 0 = 32, or 64
- * with position noise): it
+ * with position noise, Re-State or AIU on): it
  * culls the window, steps its visible rows and, when Re-State or AIU is
  * on, treats its invisible sampled rows, so no mask or index list passes
  * through memory in between.  Results equal the visibility call followed

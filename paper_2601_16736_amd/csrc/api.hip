@@ -443,9 +443,12 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     if (st != GS_OK) return st;
     st = check_noise_groups(cfg, groups, n_groups, "");
     if (st != GS_OK) return st;
-    // the fastest windows on the 3M scene: 32, and 64 with position noise,
-    // whose per-row arithmetic then runs on twice as many lanes of a wave
-    const int unit = cfg->unit != 0 ? cfg->unit : cfg->noise_enable ? 64 : 32;
+    // the fastest windows on the 3M scene: 32 for the plain step; 64 with
+    // position noise (its per-row arithmetic runs on twice as many lanes) and
+    // on Re-State or AIU calls (each wave's pass over its window's sampled
+    // invisible rows then serves twice as many rows)
+    const bool wide = cfg->noise_enable || cfg->rsr_enable || cfg->aiu_enable;
+    const int unit = cfg->unit != 0 ? cfg->unit : wide ? 64 : 32;
     if (unit != 32 && unit != 64 && unit != 128 && unit != 256)
         return fail(GS_EINVAL, "unit = %d: the view step takes 32, 64, 128 or 256 primitives per wave", cfg->unit);
     s.sched = kSchedMasked;

@@ -50,6 +50,7 @@ def test_trace_lines(capfd, monkeypatch):
     lines = [l for l in err.splitlines() if l.startswith("gsopt:")]
     assert len(lines) == 3, err
     assert lines[0].startswith("gsopt: adamw_gs_step n=3000 groups=5 schedule=masked unit=64 moments=f32 iteration=2")
-    assert lines[1].startswith("gsopt: adamw_gs_step_view n=3000 groups=5 schedule=view unit=32") and \
+    # a Re-State call: the fused step's default window is then 64
+    assert lines[1].startswith("gsopt: adamw_gs_step_view n=3000 groups=5 schedule=view unit=64") and \
         "rsr=1" in lines[1] and lines[1].endswith("views=2")
     assert lines[2].startswith("gsopt: adamw_gs_step_batched n=3000 groups=5 schedule=plan") and "scenes=1" in lines[2]
