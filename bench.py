@@ -65,7 +65,9 @@ BYTES_PER_PRIMITIVE = {"two_launch": 1, "view": 12}
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
 N_GRAD_SETS = 4
-VIEW_UNIT = 32           # primitives per wave window in the fused view step
+# primitives per wave window in the fused view step: 0 = the library's
+# default, 32 on plain steps and 64 on Re-State iterations
+VIEW_UNIT = 0
 # HBM counter summaries per path, and the sources of the kernel each covers
 TRAFFIC_FILES = {"view": os.path.join(ROOT, "profiles", "step_view_kernel_3M_traffic.json"),
                  "two_launch": os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")}
@@ -276,7 +278,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     """Times `steps` whole steps (after `warmup`) on fresh optimizer state.
     path "two_launch": gs_visibility (mask, index list and count) then the
     masked step; "view": adamw_gs_step_view, visibility fused into the step (one
-    launch, windows of VIEW_UNIT primitives).  The fused path writes no count, so its visible
+    launch, the library's default windows).  The fused path writes no count, so its visible
     counts are taken from a two-launch run on the same cameras (`counts_from`),
     whose results are bit-identical."""
     import synth
@@ -630,7 +632,7 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
 
 
 def run_sweep(gs, torch, steps: int = 100, warmup: int = 10, only_n: int = 0) -> list:
-    """The fused view step (FP32, windows of VIEW_UNIT, Morton order) over
+    """The fused view step (FP32, windows of 32, Morton order) over
     scene sizes 1M-24M at the rig's z_far 17.5, and over visible fractions
     (z_far 15, 17.5, 20, 25, infinity) at 3M.  Scenes are drawn on the
     device (means U[-10, 10]^3, other attributes N(0, 1), one gradient set
@@ -1089,7 +1091,8 @@ def main(argv=None) -> int:
             "visible_frac": head["visible_mean"] / N_PRIMS,
             "path": args.path,
             "schedule": "view windows" if args.path == "view" else "masked windows",
-            "unit": VIEW_UNIT if args.path == "view" else STEP_LAUNCH["unit"],
+            "unit": ("32 (64 on Re-State iterations)" if VIEW_UNIT == 0 else VIEW_UNIT) if args.path == "view"
+                    else STEP_LAUNCH["unit"],
         },
         "roofline": {
             "bound": "hbm",
