@@ -60,6 +60,8 @@ CASES = [  # (n, unit, bf16, rsr, aiu, noise, radius)
     (20_011, 128, True, True, False, False, False),
     (20_011, 256, False, True, True, True, True),
     (100_003, 128, False, True, False, False, False),
+    (20_011, 64, True, False, True, False, False),
+    (20_011, 64, False, False, True, True, True),
 ]
 
 
