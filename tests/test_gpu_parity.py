@@ -349,6 +349,49 @@ def test_config1_trajectory_20_steps():
         assert e <= 1e-6, f"{name}: theta drift {e:.3e} after {steps} steps"
 
 
+def test_half_schedule_dense_then_sparse():
+    """The paper's "Half" variant: plain Adam on every primitive while the
+    set grows (the dense schedule), Sparse Adam afterwards (masked).  The
+    caller switches schedules between calls; the step counts carry over, so
+    after the dense phase every t equals its length.  GPU and oracle run free
+    from the same start: attributes within 1e-6, step counts exact."""
+    n, dense_steps, sparse_steps = 50_000, 6, 6
+    spec = synth.GROUPS_59
+    scene = synth.scene_uniform(n, seed=3, groups=spec)
+    st = make_state(gs, n, spec, 3, nonzero_state=False)
+    for (name, *_), g in zip(spec, st.groups):
+        g.param.copy_(torch.from_numpy(scene.params[name]))
+    og = oracle_groups(st.host(), spec, st.groups)
+    t_ref = np.zeros(n, np.int32)
+    ones = np.ones(n, np.uint8)
+    for s in range(dense_steps + sparse_steps):
+        dense = s < dense_steps
+        mask = ones if dense else synth.bernoulli_mask(n, 0.3, 3, s)
+        gr = synth.grads(n, spec, mask, 3, s)
+        for (name, *_), g, o in zip(spec, st.groups, og):
+            g.grad.copy_(torch.from_numpy(gr[name]))
+            o.grad[:] = gr[name]
+        if dense:
+            cfg = gs.StepConfig(iteration=s, seed=3, schedule=gs.GS_SCHED_DENSE, unit=64)
+            gs.adamw_gs_step(st.groups, n, st.t, cfg)
+            oracle.adamw_gs_step(og, n, None, t_ref, oracle_config(cfg))
+        else:
+            cfg = gs.StepConfig(iteration=s, seed=3, schedule=gs.GS_SCHED_MASKED, unit=32)
+            d_mask = torch.from_numpy(mask).to(DEV)
+            gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask)
+            oracle.adamw_gs_step(og, n, mask, t_ref, oracle_config(cfg))
+        if s == dense_steps - 1:
+            torch.cuda.synchronize()
+            assert (st.t.cpu().numpy() == dense_steps).all()
+    torch.cuda.synchronize()
+    after = st.host()
+    np.testing.assert_array_equal(after["_t"], t_ref)
+    assert (t_ref > dense_steps).any() and (t_ref == dense_steps).any()
+    for (name, *_), o in zip(spec, og):
+        e = theta_err(after[name]["param"], o.param)
+        assert e <= 1e-6, f"{name}: theta drift {e:.3e} after the dense and sparse phases"
+
+
 # ---------------------------------------------------------------- full size
 def test_full_size_scene_sampled_rows():
     """3M-primitive scene (means U[-10,10]^3, rig camera, z_far 17.5): the
