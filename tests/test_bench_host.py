@@ -50,6 +50,21 @@ def test_committed_traffic_summaries_name_the_sources_they_cover():
         assert d["bytes_per_launch"] == pytest.approx(d["fetched"] + d["written"])
 
 
+def test_committed_traffic_is_close_to_the_algorithmic_bytes():
+    """The committed counter figure is per launch of the headline instance
+    (the plain steps).  It must lie between the algorithmic bytes and 10 %
+    above them: a figure taken from another instance of the kernel, e.g. a
+    Re-State launch, which also moves its sampled invisible rows, lands
+    outside."""
+    import re
+    md = open(os.path.join(os.path.dirname(bench.TRAFFIC_FILES["view"]), "step_view_kernel_3M_traffic.md")).read()
+    nv = float(re.search(r"visible (\d+) x 1660 B", md).group(1))
+    for path in ("view", "two_launch"):
+        d = json.load(open(bench.TRAFFIC_FILES[path]))
+        alg = nv * bench.BYTES_PER_VISIBLE["f32"] + bench.N_PRIMS * bench.BYTES_PER_PRIMITIVE[path]
+        assert 1.0 <= d["bytes_per_launch"] / alg <= 1.10, (path, d["bytes_per_launch"] / alg)
+
+
 def test_gpu_clocks_never_raises():
     c = bench.gpu_clocks()
     assert c is None or all(isinstance(k, str) and isinstance(v, str) for k, v in c.items())
