@@ -18,14 +18,15 @@ void clear_error();
 namespace {
 
 #ifndef GS_MUT_UNIT
-#define GS_MUT_UNIT 128
+#define GS_MUT_UNIT 64
 #endif
 #ifndef GS_MUT_UNROLL
 #define GS_MUT_UNROLL 8
 #endif
 // GS_MUT_UNIT: rows per wave of the prune.  GS_MUT_UNROLL: loads in flight
-// per lane in the row moves.  128 rows and 8 loads were the fastest for
-// pruning 10 % of the 3M scene (805 us, against 838 us with 512 and 4).
+// per lane in the row moves.  Pruning 10 % of a 3M-row, 59-attribute FP32
+// state took 838 us with 512 rows and 4 loads, 802 us with 128 and 8,
+// 786 us with 64 and 8, 817 us with 256 and 8, and 846 us with 128 and 16.
 constexpr int kMutUnit = GS_MUT_UNIT;
 constexpr int kMaxArrays = 3 * GS_MAX_GROUPS + 1;
 constexpr size_t kWsAlign = 256;
