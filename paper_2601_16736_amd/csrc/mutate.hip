@@ -3,12 +3,14 @@
 // optimizer state.  Both are row copies driven by a per-wave row list in LDS,
 // walked like the step's groups: consecutive lanes move consecutive chunks
 // of a row, several chunks in flight per lane.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 
 #include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
+#include "trace.h"
 
 namespace gs {
 
@@ -158,21 +160,26 @@ __global__ void set_zero_kernel(int32_t* p) { *p = 0; }
 constexpr int kAppendUnit = GS_APPEND_UNIT;
 static_assert(kAppendUnit >= 1 && kAppendUnit <= 1024, "append unit");
 
-// new rows n + [unit*64, unit*64 + 64): clones of src_idx, state zeroed
-__global__ __launch_bounds__(kBlock) void append_kernel(KMut M)
+// new rows n + [u*kAppendUnit, (u+1)*kAppendUnit) for each unit u of the
+// wave: clones of src_idx, state zeroed.  The grid is capped at what one
+// dispatch holds; a wave then takes every (grid waves)-th unit.
+__global__ __launch_bounds__(kBlock) void append_kernel(KMut M, int64_t units)
 {
     __shared__ int s_row[kWavesPerBlock][kAppendUnit];
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int64_t j0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kAppendUnit;
-    if (j0 >= M.k) return;
-    const int nrows = (int)min((int64_t)kAppendUnit, M.k - j0);
-    for (int j = lane; j < nrows; j += kWave) {
-        const int32_t s = M.src_idx[j0 + j];
-        s_row[wave][j] = (s >= 0 && s < M.n) ? s : -1;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave; u < units;
+         u += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t j0 = u * kAppendUnit;
+        const int nrows = (int)min((int64_t)kAppendUnit, M.k - j0);
+        wave_sync();   // the previous unit's rows are done with
+        for (int j = lane; j < nrows; j += kWave) {
+            const int32_t s = M.src_idx[j0 + j];
+            s_row[wave][j] = (s >= 0 && s < M.n) ? s : -1;
+        }
+        wave_sync();
+        move_all(M, nrows, s_row[wave], M.n + j0, lane);
     }
-    wave_sync();
-    move_all(M, nrows, s_row[wave], M.n + j0, lane);
 }
 
 size_t align_up(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
@@ -330,8 +337,8 @@ extern "C" gs_status gs_append(const gs_group* groups, int32_t n_groups, int32_t
     M.k = k;
     M.src_idx = src_idx;
     const int64_t units = (k + kAppendUnit - 1) / kAppendUnit;
-    const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(append_kernel, dim3(blocks), dim3(kBlock), 0, stream, M);
+    const unsigned blocks = (unsigned)std::min<int64_t>((units + kWavesPerBlock - 1) / kWavesPerBlock, kMaxGridBlocks);
+    hipLaunchKernelGGL(append_kernel, dim3(blocks), dim3(kBlock), 0, stream, M, units);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
 }

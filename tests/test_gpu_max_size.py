@@ -134,3 +134,28 @@ def test_max_size_fused_view_step():
     touched = ref_mask.astype(bool) | oracle.rsr_sample_mask(cfg.seed, cfg.iteration, n, cfg.rsr_ratio,
                                                              ids=rows).astype(bool)
     compare(after, before, og, spec, t_ref, touched, False, "max-size view")
+
+
+def test_max_size_append():
+    """gs_append up to n + k = 2^31 - 1 rows.  One wave per unit would need
+    more work-items than a dispatch holds, so the grid is capped and its
+    waves stride over the remaining units.  Every new row is a clone of its
+    source with zero state; the old rows are untouched."""
+    n = 100
+    k = N_MAX - n
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(91)
+    p = torch.zeros((n + k, 1), device=DEV)
+    p[:n, 0] = torch.arange(1, n + 1, dtype=torch.float32, device=DEV)     # source s holds s + 1
+    m = torch.full((n + k, 1), 7.0, device=DEV)
+    v = torch.full((n + k, 1), 7.0, device=DEV)
+    t = torch.full((n + k,), 5, dtype=torch.int32, device=DEV)
+    src = torch.randint(0, n, (k,), generator=gen, device=DEV, dtype=torch.int32)
+    print(f"append n={n} k={k}", flush=True)
+    gs.gs_append([gs.Group(p, None, m, v, 1e-3)], gs.GS_MOMENT_F32, n, src, t)
+    torch.cuda.synchronize()
+    assert torch.equal(p[n:, 0], src.to(torch.float32) + 1)
+    assert int((m[n:] != 0).sum()) == 0 and int((v[n:] != 0).sum()) == 0 and int((t[n:] != 0).sum()) == 0
+    assert torch.equal(p[:n, 0], torch.arange(1, n + 1, dtype=torch.float32, device=DEV))
+    assert int((m[:n] != 7).sum()) == 0 and int((v[:n] != 7).sum()) == 0 and int((t[:n] != 5).sum()) == 0
+    del p, m, v, t, src
