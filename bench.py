@@ -54,6 +54,11 @@ import numpy as np  # noqa: E402
 STEP_LAUNCH = {"schedule": 2, "unit": 32}           # masked schedule, windows of 32 primitives
 
 N_PRIMS = 3_000_000
+MCMC_N = 6_000_000                 # the MCMC-shaped workload's cap
+BATCH_SIZE_RANGE = (2e5, 4e6)      # the batched workload's scene sizes (log-uniform)
+DEVICE = "cuda:0"
+# the unfused comparator is checked against the fused step before it is timed
+CHECK_UNFUSED = True
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per visible primitive of the step: theta r/w, g r, m r/w,
 # v r/w over 59 elements; t r/w
@@ -141,44 +146,93 @@ def measured_traffic(order: str, moments: str, path: str = "view"):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cams, order, budget_s: float = 12.0, sample_n: int = 300_000):
-    """The FP64 oracle (single-threaded C) on the first `sample_n` primitives of
-    the same scene, same cameras and hyper-parameters, stepped until the time
-    budget is spent."""
+def host_cores() -> int:
+    """Host threads the CPU baseline uses: the cores this process may run on,
+    at most 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(scene, cams, order, budget_s: float = 12.0, sample_n: int = 0, cores: int = 0):
+    """The FP64 oracle, unchanged, on the same scene, cameras and
+    hyper-parameters: each step is the visibility predicate of the step's
+    view and the AdamW-GS step.  The primitives are split into one
+    contiguous shard per host thread (every primitive's step depends only on
+    its own rows; each shard passes its rows' scene indices, so the Re-State
+    draws are those of the unsharded step), and the threads run the oracle's
+    C functions concurrently (ctypes releases the GIL during a call).  Steps
+    run until half the budget is spent on all `cores` threads, then until the
+    other half is spent on one thread, from where the first run stopped.
+    sample_n = 0 takes the whole scene."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     from synth import GROUPS_59
+    n = scene.n if sample_n <= 0 else min(sample_n, scene.n)
+    cores = cores or host_cores()
     groups = []
     for name, dim, lr, dar in GROUPS_59:
-        p = scene.params[name][:sample_n].astype(np.float64)
+        p = np.ascontiguousarray(scene.params[name][:n], dtype=np.float64)
         groups.append(oracle.Group(p, np.zeros_like(p), np.zeros_like(p), np.zeros_like(p), lr, dar_kind=dar,
                                    dar_lambda=LAMBDA_O if dar == 1 else LAMBDA_S, dar_clip=CLIP))
-    t = np.zeros(sample_n, np.int32)
+    t = np.zeros(n, np.int32)
     rng = np.random.default_rng(1234)
     for G in groups:
         G.grad[:] = 1e-3 * rng.standard_normal(G.grad.shape)
-    updates, elapsed, steps = 0, 0.0, 0
-    while elapsed < budget_s:
-        c = cams[order[steps % len(order)]]
-        cam = oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
-        means32 = groups[0].param.astype(np.float32)
-        cfg = oracle.Config(reg_norm=REG_NORM, seed=0, iteration=steps, rsr_enable=steps % RSR_EVERY == 0,
-                            rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2)
-        t0 = time.perf_counter()
-        mask = oracle.visibility(means32, cam)
-        oracle.adamw_gs_step(groups, sample_n, mask, t, cfg)
-        elapsed += time.perf_counter() - t0
-        updates += int(mask.sum()) * 59
-        steps += 1
-    return {"value": updates / elapsed, "unit": "attr-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_n} primitives of the scene, {steps} steps (visibility + step), "
-                      f"{elapsed:.1f} s, 1 thread"}
+
+    def shards(k):
+        bounds = np.linspace(0, n, k + 1).astype(np.int64)
+        out = []
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            if b > a:
+                sub = [oracle.Group(G.param[a:b], G.grad[a:b], G.m[a:b], G.v[a:b], G.lr, dar_kind=G.dar_kind,
+                                    dar_lambda=G.dar_lambda, dar_clip=G.dar_clip) for G in groups]
+                out.append((sub, t[a:b], np.arange(a, b, dtype=np.int64)))
+        return out
+
+    def one_shard(sh, cam, cfg):
+        sub, ts, ids = sh
+        mask = oracle.visibility(sub[0].param.astype(np.float32), cam)
+        oracle.adamw_gs_step(sub, len(ids), mask, ts, cfg, ids=ids)
+        return int(mask.sum())
+
+    step = 0
+
+    def run(k_threads, budget):
+        nonlocal step
+        parts = shards(k_threads)
+        updates, elapsed, steps = 0, 0.0, 0
+        with ThreadPoolExecutor(max_workers=k_threads) as pool:
+            while elapsed < budget:
+                c = cams[order[step % len(order)]]
+                cam = oracle.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+                cfg = oracle.Config(reg_norm=REG_NORM, seed=0, iteration=step, rsr_enable=step % RSR_EVERY == 0,
+                                    rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2)
+                t0 = time.perf_counter()
+                vis = sum(pool.map(lambda sh: one_shard(sh, cam, cfg), parts))
+                elapsed += time.perf_counter() - t0
+                updates += vis * 59
+                steps += 1
+                step += 1
+        return updates / elapsed, steps, elapsed
+
+    v_all, s_all, e_all = run(cores, budget_s / 2)
+    v_one, s_one, e_one = run(1, budget_s / 2)
+    return {"value": v_all, "unit": "attr-updates/s", "cores": cores, "kind": "oracle",
+            "value_1_thread": v_one, "speedup_over_1_thread": v_all / v_one,
+            "sample": f"{n} primitives of the scene (index order), visibility + step per step; "
+                      f"{s_all} steps in {e_all:.1f} s on {cores} threads (one contiguous shard each), "
+                      f"then {s_one} steps in {e_one:.1f} s on 1 thread"}
 
 
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
     import torch
-    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=DEVICE)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -191,36 +245,39 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
     return 0
 
 
-def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
-    """Bandwidth of plain contiguous kernels on this device (libgsprobe):
+PROBE_DEFAULT = (16, 4, 1, 1, 0)          # width, items, nt_load, nt_store, blocks
+PROBE_SHAPES = [(w, it, ntl, nts, b) for w in (16, 8) for it in (2, 4, 8, 16) for ntl in (1, 0) for nts in (1, 0)
+                for b in (0, 1024, 2048)]
+
+
+def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None) -> dict:
+    """Bandwidth of plain contiguous kernels on this device (bench_probe):
     the step's 4-read / 3-write mix over four arrays of `nbytes`, a copy and
     a read, each timed with HIP events over `reps` launches after 3 untimed
-    ones.  Four arrays of 256 MiB exceed the 256 MB Infinity Cache, so every
-    pass streams from HBM."""
-    import ctypes
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2601_16736_amd", "libgsprobe.so"))
-    vp, i64 = ctypes.c_void_p, ctypes.c_int64
-    lib.gsprobe_rmw_4r3w.argtypes = [vp, vp, vp, vp, i64, vp]
-    lib.gsprobe_copy.argtypes = [vp, vp, i64, vp]
-    lib.gsprobe_read.argtypes = [vp, i64, vp, vp]
-    dev = torch.device("cuda:0")
+    ones, for every launch shape in `shapes` (access width, accesses in
+    flight per thread, non-temporal hints on loads / stores, one-shot or
+    resident grid).  Reports the fixed default shape and the best shape of
+    each mix.  Four arrays of 256 MiB exceed the 256 MB Infinity Cache, so
+    every pass streams from HBM."""
+    import bench_probe
+    lib = bench_probe.load()
+    vp = __import__("ctypes").c_void_p
+    dev = torch.device(DEVICE)
     arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
     sink = torch.zeros(4, device=dev)
     n16 = nbytes // 16
     stream = torch.cuda.current_stream()
     sp = vp(stream.cuda_stream)
     ptr = [a.data_ptr() for a in arrs]
-    calls = {
-        "rmw_4r3w": (lambda: lib.gsprobe_rmw_4r3w(ptr[0], ptr[1], ptr[2], ptr[3], n16, sp), 7 * nbytes),
-        "copy": (lambda: lib.gsprobe_copy(ptr[0], ptr[1], n16, sp), 2 * nbytes),
-        "read": (lambda: lib.gsprobe_read(ptr[0], n16, sink.data_ptr(), sp), nbytes),
-    }
-    out = {}
-    for name, (fn, moved) in calls.items():
+    shapes = PROBE_SHAPES if shapes is None else shapes
+    if PROBE_DEFAULT not in shapes:
+        shapes = [PROBE_DEFAULT] + list(shapes)
+
+    def timed(fn) -> float:
         ev = TimingEvents(reps)
         for _ in range(3):
             if fn() != 0:
-                raise RuntimeError(f"gsprobe {name} failed")
+                raise RuntimeError("gsprobe launch failed")
         for j in range(reps):
             ev.record("start", j, stream)
             fn()
@@ -228,7 +285,28 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
         torch.cuda.synchronize()
         sec = float(np.mean([ev.ms(j) for j in range(reps)])) * 1e-3
         ev.close()
-        out[f"{name}_GBps"] = moved / sec / 1e9
+        return sec
+
+    table = {"rmw_4r3w": {}, "copy": {}, "read": {}}
+    for (w, it, ntl, nts, b) in shapes:
+        key = f"w{w}_i{it}_ntl{ntl}_nts{nts}_b{b}"
+        table["rmw_4r3w"][key] = 7 * nbytes / timed(
+            lambda: lib.gsprobe_rmw_4r3w_cfg(ptr[0], ptr[1], ptr[2], ptr[3], n16, w, it, ntl, nts, b, sp)) / 1e9
+        table["copy"][key] = 2 * nbytes / timed(
+            lambda: lib.gsprobe_copy_cfg(ptr[0], ptr[1], n16, w, it, ntl, nts, b, sp)) / 1e9
+        if nts == 1:                    # a read has no stores: one entry per load hint
+            table["read"][key] = nbytes / timed(
+                lambda: lib.gsprobe_read_cfg(ptr[0], n16, sink.data_ptr(), w, it, ntl, b, sp)) / 1e9
+    dkey = "w{}_i{}_ntl{}_nts{}_b{}".format(*PROBE_DEFAULT)
+    out = {}
+    for mix, t in table.items():
+        best = max(t, key=t.get)
+        out[f"{mix}_GBps"] = t[dkey]
+        out[f"{mix}_best_GBps"] = t[best]
+        out[f"{mix}_best_shape"] = best
+    out["shapes_timed"] = len(shapes)
+    out["default_shape"] = dkey
+    out["table"] = table
     del arrs, sink
     torch.cuda.empty_cache()
     return out
@@ -256,7 +334,7 @@ class SceneOnDevice:
 
     def __init__(self, gs, torch, scene, order: str):
         import synth
-        dev = torch.device("cuda:0")
+        dev = torch.device(DEVICE)
         self.params = [torch.from_numpy(scene.params[name]).to(dev) for name, *_ in synth.GROUPS_59]
         gen = torch.Generator(device=dev)
         gen.manual_seed(0)
@@ -282,7 +360,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     counts are taken from a two-launch run on the same cameras (`counts_from`),
     whose results are bit-identical."""
     import synth
-    dev = torch.device("cuda:0")
+    dev = torch.device(DEVICE)
     mdt = torch.bfloat16 if moments == "bf16" else torch.float32
     groups = []
     for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads):
@@ -303,7 +381,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
 
     def one_step(k: int, slot: int = -1):
         cnt = counts[k:k + 1]
-        gs.gs_visibility(means, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        gs.gs_visibility(means, gcams[order[k % len(order)]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
         for G, sets in zip(groups, sd.grads):
             G.grad = sets[k % N_GRAD_SETS]
         cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
@@ -323,7 +401,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
                             stochastic_round=True, unit=VIEW_UNIT)
         if slot >= 0:
             ev.record("start", slot, stream)
-        gs.adamw_gs_step_view(groups, N_PRIMS, t, cfg, means, gcams[order[k]], stream=stream)
+        gs.adamw_gs_step_view(groups, N_PRIMS, t, cfg, means, gcams[order[k % len(order)]], stream=stream)
         if slot >= 0:
             ev.record("end", slot, stream)
 
@@ -364,7 +442,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     }
 
 
-def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, warmup: int = 5):
+def run_unfused(gs, torch, sd: SceneOnDevice, cams, steps: int = 100, warmup: int = 5):
     """What fusion buys: the same AdamW-GS step written as one-op-per-pass
     PyTorch eager kernels over the compacted visible rows.  The library's
     gs_visibility gives the index list; its count is read to the host, as an
@@ -374,9 +452,11 @@ def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, war
     back.  Re-State iterations rescale m and v of a Bernoulli sample drawn
     with torch's generator.  FP32 moments.  A comparator, not part of the
     library: before it is timed, three steps of it are checked against the
-    fused step from the same state."""
+    fused step from the same state.  The camera order is the leg's own,
+    sized to its own steps."""
     import synth
-    dev = torch.device("cuda:0")
+    dev = torch.device(DEVICE)
+    order = synth.camera_order(len(cams), warmup + steps, seed=0)
     b1, b2, eps = 0.9, 0.999, 1e-15
     gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
     mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
@@ -396,7 +476,7 @@ def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, war
     def eager_step(groups, t, k):
         for G, sets in zip(groups, sd.grads):
             G.grad = sets[k % N_GRAD_SETS]
-        gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt)
+        gs.gs_visibility(groups[0].param, gcams[order[k % len(order)]], mask=mask, vis_idx=idx, vis_count=cnt)
         if k % RSR_EVERY == 0:
             picked = torch.nonzero(torch.rand(N_PRIMS, generator=gen, device=dev) < RSR_P).squeeze(1)
             for G in groups:
@@ -424,24 +504,26 @@ def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, war
             G.exp_avg[rows] = m
             G.exp_avg_sq[rows] = v
 
-    # the comparator computes the same step: three steps from the same state
-    ref, t_ref = fresh()
-    mine, t_mine = fresh()
-    for k in (1, 2, 3):
-        for G, sets in zip(ref, sd.grads):
-            G.grad = sets[k % N_GRAD_SETS]
-        gs.gs_visibility(ref[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt)
-        gs.adamw_gs_step(ref, N_PRIMS, t_ref, gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, **STEP_LAUNCH),
-                         visible=mask, vis_idx=idx, vis_count=cnt)
-        eager_step(mine, t_mine, k)
-    torch.cuda.synchronize()
-    worst = max(float(((A.param - B.param).abs() / B.param.abs().clamp(min=1.0)).max()) for A, B in zip(mine, ref))
-    moved = max(float((B.param - p).abs().max()) for B, p in zip(ref, sd.params))
-    rows_checked = int((t_ref > 0).sum())
-    if not torch.equal(t_mine, t_ref) or worst > 1e-5 or moved == 0.0 or rows_checked == 0:
-        raise RuntimeError(f"the unfused comparator does not reproduce the fused step (max err {worst:.3g}, "
-                           f"fused step moved theta by up to {moved:.3g}, {rows_checked} rows stepped)")
-    del ref, t_ref, mine, t_mine
+    worst = moved = rows_checked = None
+    if CHECK_UNFUSED:
+        # the comparator computes the same step: three steps from the same state
+        ref, t_ref = fresh()
+        mine, t_mine = fresh()
+        for k in (1, 2, 3):
+            for G, sets in zip(ref, sd.grads):
+                G.grad = sets[k % N_GRAD_SETS]
+            gs.gs_visibility(ref[0].param, gcams[order[k % len(order)]], mask=mask, vis_idx=idx, vis_count=cnt)
+            gs.adamw_gs_step(ref, N_PRIMS, t_ref, gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, **STEP_LAUNCH),
+                             visible=mask, vis_idx=idx, vis_count=cnt)
+            eager_step(mine, t_mine, k)
+        torch.cuda.synchronize()
+        worst = max(float(((A.param - B.param).abs() / B.param.abs().clamp(min=1.0)).max()) for A, B in zip(mine, ref))
+        moved = max(float((B.param - p).abs().max()) for B, p in zip(ref, sd.params))
+        rows_checked = int((t_ref > 0).sum())
+        if not torch.equal(t_mine, t_ref) or worst > 1e-5 or moved == 0.0 or rows_checked == 0:
+            raise RuntimeError(f"the unfused comparator does not reproduce the fused step (max err {worst:.3g}, "
+                               f"fused step moved theta by up to {moved:.3g}, {rows_checked} rows stepped)")
+        del ref, t_ref, mine, t_mine
 
     groups, t = fresh()
     total = warmup + steps
@@ -462,6 +544,83 @@ def run_unfused(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 100, war
             "check_rows_stepped": rows_checked, "check_max_theta_move": moved}
 
 
+def run_config1(gs, torch, steps: int = 20, warmup: int = 5, n: int = 100_000) -> dict:
+    """The small plain workload: 100k Gaussians of 59 FP32 attributes, all
+    drawn N(0, 1); per step a Bernoulli(0.3) visibility mask (seed 0) and
+    gradients N(0, 1e-3) on the visible rows only, as synth draws them; RSR
+    off (its 100-step interval exceeds the run).  Every step's mask and
+    gradients are uploaded before timing.  The step is adamw_gs_step with
+    the mask (masked windows of 32), timed per launch with HIP events on the
+    launch stream.  The optimizer state (94 MB) fits in the 256 MB Infinity
+    Cache, so this figure is cache-resident, not an HBM figure."""
+    import synth
+    dev = torch.device(DEVICE)
+    g0 = synth.rng(0, 1)
+    params = {name: g0.standard_normal((n, dim)).astype(np.float32) for name, dim, _, _ in synth.GROUPS_59}
+    masks, grads = [], []
+    for k in range(warmup + steps):
+        m = synth.bernoulli_mask(n, 0.3, seed=0, step=k)
+        gk = synth.grads(n, synth.GROUPS_59, m, seed=0, step=k)
+        masks.append(torch.from_numpy(m).to(dev))
+        grads.append([torch.from_numpy(gk[name]).to(dev) for name, *_ in synth.GROUPS_59])
+    groups = [gs.Group(torch.from_numpy(params[name]).to(dev), grads[0][j], torch.zeros((n, dim), device=dev),
+                       torch.zeros((n, dim), device=dev), lr, dar_kind=dar,
+                       dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+              for j, (name, dim, lr, dar) in enumerate(synth.GROUPS_59)]
+    t = torch.zeros(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = TimingEvents(steps)
+    torch.cuda.synchronize()
+    t0 = 0.0
+    for k in range(warmup + steps):
+        if k == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for G, gk in zip(groups, grads[k]):
+            G.grad = gk
+        cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, **STEP_LAUNCH)
+        j = k - warmup
+        if j >= 0:
+            ev.record("start", j, stream)
+        gs.adamw_gs_step(groups, n, t, cfg, visible=masks[k], stream=stream)
+        if j >= 0:
+            ev.record("end", j, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+    ev.close()
+    nv = np.array([int(masks[k].sum().item()) for k in range(warmup, warmup + steps)], np.int64)
+    byts = nv * BYTES_PER_VISIBLE["f32"] + n * BYTES_PER_PRIMITIVE["two_launch"]
+    del groups, t, masks, grads
+    torch.cuda.empty_cache()
+    return {"workload": "100k Gaussians x 59 FP32 attributes, Bernoulli(0.3) visibility per step, "
+                        "gradients N(0, 1e-3) on visible rows, masked step (windows of 32); cache-resident",
+            "steps": steps, "value": float(nv.sum() * 59 / wall), "ms_per_step": wall / steps * 1e3,
+            "kernel_attr_updates_per_s": float(nv.sum() * 59 / d.sum()),
+            "step_kernel_us": float(d.mean() * 1e6), "visible_mean": float(nv.mean()),
+            "achieved_GBps_cache_resident": float(byts.sum() / d.sum() / 1e9)}
+
+
+def guarded(name: str, fn, *args, **kwargs):
+    """Runs one variant leg; a failure becomes {"error": ...} in the JSON
+    line instead of ending the run (the headline, its roofline and the CPU
+    baseline are printed whatever the variants do)."""
+    import traceback
+    print(f"bench: variant {name}", file=sys.stderr, flush=True)
+    try:
+        return fn(*args, **kwargs)
+    except Exception as e:  # noqa: BLE001  (any failure of a context leg)
+        tb = traceback.format_exc(limit=4)
+        print(f"bench: variant {name} failed: {e!r}\n{tb}", file=sys.stderr, flush=True)
+        try:
+            import torch
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        except Exception:  # noqa: BLE001
+            pass
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 # position-noise and AIU settings of the widened-row measurements (the paper
 # defers lambda_mu, lambda_t and eta_{R_o} to the 3DGS-MCMC settings and gives
 # Pro_AIU / eta_AIU only per table; these are those defaults and round values)
@@ -469,7 +628,7 @@ NOISE_KW = dict(noise_enable=True, noise_groups=(0, 1, 2, 3), noise_lr=5e5, nois
 AIU_RATIO, AIU_SCALE = 0.05, 1.0
 
 
-def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, warmup: int = 10) -> dict:
+def run_next_rows(gs, torch, sd: SceneOnDevice, cams, steps: int = 200, warmup: int = 10) -> dict:
     """The widened rows on the 3M Morton scene with FP32 moments, each timed
     with HIP events on the launch stream and read against its algorithmic
     bytes:
@@ -483,9 +642,11 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     - pruning 10 % of the primitives (gs_prune) and appending 5 % as clones
       (gs_append).
     The view steps also write their mask (1 B per primitive, counted), from
-    which the visible counts are read outside the timed region."""
+    which the visible counts are read outside the timed region.  The camera
+    order is the leg's own, sized to its own steps."""
     import synth
-    dev = torch.device("cuda:0")
+    dev = torch.device(DEVICE)
+    order = synth.camera_order(len(cams), warmup + steps, seed=0)
     gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
     stream = torch.cuda.current_stream()
     n = N_PRIMS
@@ -515,7 +676,7 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
             cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
                                 rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, **extra)
             view = [gcams[order[(k + 53 * j) % len(order)]] for j in range(n_cams)] if n_cams > 1 \
-                else gcams[order[k]]
+                else gcams[order[k % len(order)]]
             if aiu and k >= warmup:
                 # expected AIU rows of this step: p x (invisible rows with t > 0), t before the step
                 aiu_t = (t > 0)
@@ -581,7 +742,7 @@ def run_next_rows(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 200, w
     m0 = torch.zeros(n, dtype=torch.uint8, device=dev)
     for k in range(3):
         gs.adamw_gs_step_view(src, n, t, gs.StepConfig(reg_norm=REG_NORM, iteration=k, unit=VIEW_UNIT),
-                              src[0].param, gcams[order[k]], visible_out=m0)
+                              src[0].param, gcams[order[k % len(order)]], visible_out=m0)
     gen = torch.Generator(device=dev)
     gen.manual_seed(17)
     keep = (torch.rand(n, generator=gen, device=dev) < 0.9).to(torch.uint8)
@@ -640,7 +801,7 @@ def run_sweep(gs, torch, steps: int = 100, warmup: int = 10, only_n: int = 0) ->
     timed region, give the algorithmic bytes (1660 B per visible + 13 B per
     primitive)."""
     import synth
-    dev = torch.device("cuda:0")
+    dev = torch.device(DEVICE)
     stream = torch.cuda.current_stream()
     out = []
 
@@ -672,7 +833,7 @@ def run_sweep(gs, torch, steps: int = 100, warmup: int = 10, only_n: int = 0) ->
             j = k - warmup
             if j >= 0:
                 ev.record("start", j, stream)
-            gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, gcams[order[k]], visible_out=mask,
+            gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, gcams[order[k % len(order)]], visible_out=mask,
                                   stream=stream)
             if j >= 0:
                 ev.record("end", j, stream)
@@ -720,8 +881,8 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
     per-scene adamw_gs_step calls with FP32 and with BF16 moments.  Every
     form includes the compaction of the compacted scenes' masks."""
     import synth
-    dev = torch.device("cuda:0")
-    sizes, ratios = synth.batch_scene_sizes(16, seed=0)
+    dev = torch.device(DEVICE)
+    sizes, ratios = synth.batch_scene_sizes(16, *BATCH_SIZE_RANGE, seed=0)
     dims = [d for _, d, _, _ in synth.GROUPS_59]
     gen = torch.Generator(device=dev)
     gen.manual_seed(5)
@@ -817,8 +978,8 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10, path: str = "t
     (`counts_from`), whose end state it must reproduce bit for bit (the
     returned digest)."""
     import synth
-    dev = torch.device("cuda:0")
-    n = 6_000_000
+    dev = torch.device(DEVICE)
+    n = MCMC_N
     k_reloc = n // 100
     means = synth.scene_clustered(n, seed=0, groups=[("means", 3, 0.0, 0)]).params["means"]
     gen = torch.Generator(device=dev)
@@ -855,9 +1016,9 @@ def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10, path: str = "t
                       rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2)
         if path == "view":
             gs.adamw_gs_step_view(groups, n, t, gs.StepConfig(**common, unit=VIEW_UNIT), groups[0].param,
-                                  gcams[order[k]], stream=stream)
+                                  gcams[order[k % len(order)]], stream=stream)
         else:
-            gs.gs_visibility(groups[0].param, gcams[order[k]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+            gs.gs_visibility(groups[0].param, gcams[order[k % len(order)]], mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
             gs.adamw_gs_step(groups, n, t, gs.StepConfig(**common, **STEP_LAUNCH), visible=mask, vis_idx=idx,
                              vis_count=cnt, stream=stream)
         if slot >= 0:
@@ -924,6 +1085,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--probe-sweep", action="store_true",
+                    help="only time the streaming probes over every launch shape (one JSON line with the table)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
     ap.add_argument("--mcmc-only", action="store_true",
@@ -945,6 +1108,10 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.probe_sweep:
+        import torch
+        print(json.dumps(stream_ceilings(torch)), flush=True)
+        return 0
     if args.batched_only:
         import torch
         import paper_2601_16736_amd as gs
@@ -1009,16 +1176,18 @@ def main(argv=None) -> int:
                     path="two_launch", keep_state=args.path == "view")
     two_counts = two.pop("counts")
     variants = []
+    same_as_two_launch = None
     if args.path == "view":
         print(f"bench: {args.order} order, {args.moments} moments, visibility fused into the step: "
               f"{args.steps} steps", file=sys.stderr, flush=True)
         head = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup,
                          path="view", counts_from=two_counts, keep_state=True)
         head.pop("counts")
-        same = same_state(torch, two.pop("state"), head.pop("state"))
+        same_as_two_launch = same_state(torch, two.pop("state"), head.pop("state"))
         torch.cuda.empty_cache()
-        if not same:
-            raise RuntimeError("the fused and two-launch paths ended in different states")
+        if not same_as_two_launch:
+            print("bench: WARNING: the fused and two-launch paths ended in different states", file=sys.stderr,
+                  flush=True)
         two.update({"order": args.order, "moments": args.moments, "path": "two_launch",
                     "frac": two["achieved_GBps"] / HBM_PEAK_GBS})
         variants.append(two)
@@ -1026,45 +1195,49 @@ def main(argv=None) -> int:
         two.pop("state")
         head = two
     if not args.no_variants:
-        for o, mo in (("index", "f32"), ("morton", "f32"), ("morton", "bf16"), ("index", "bf16")):
-            if (o, mo) == (args.order, args.moments):
-                continue
+        def layout_leg(o, mo):
             if o not in layouts:
                 layouts[o] = SceneOnDevice(gs, torch, scene, o)
-            print(f"bench: variant {o} order, {mo} moments", file=sys.stderr, flush=True)
             fused_too = o == "morton"
             r = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup, keep_state=fused_too)
             counts = r.pop("counts")
             r.update({"order": o, "moments": mo, "path": "two_launch", "frac": r["achieved_GBps"] / HBM_PEAK_GBS})
+            out = [r]
             if fused_too:
-                print(f"bench: variant {o} order, {mo} moments, visibility fused into the step",
-                      file=sys.stderr, flush=True)
                 f = run_steps(gs, torch, layouts[o], cams, order, mo, args.steps, args.warmup, path="view",
                               counts_from=counts, keep_state=True)
                 f.pop("counts")
-                if not same_state(torch, r.pop("state"), f.pop("state")):
-                    raise RuntimeError(f"{o}/{mo}: the fused and two-launch paths ended in different states")
+                f["same_state_as_two_launch"] = same_state(torch, r.pop("state"), f.pop("state"))
                 torch.cuda.empty_cache()
                 f.update({"order": o, "moments": mo, "path": "view", "frac": f["achieved_GBps"] / HBM_PEAK_GBS})
-                variants.append(f)
+                out.insert(0, f)
             else:
                 r.pop("state")
-            variants.append(r)
-        print("bench: variant widened rows (noise, AIU, multi-view, prune/append)", file=sys.stderr, flush=True)
-        variants.append({"next_rows": run_next_rows(gs, torch, layouts["morton"], cams, order)})
-        print("bench: variant unfused eager comparator", file=sys.stderr, flush=True)
-        unf = run_unfused(gs, torch, layouts["morton"], cams, order)
-        fused_ms = head["ms_per_step"] if (args.order, args.moments) == ("morton", "f32") else None
-        unf["fused_speedup"] = unf["ms_per_step"] / fused_ms if fused_ms else None
-        variants.append({"unfused_comparator": unf})
+            return out
+
+        for o, mo in (("index", "f32"), ("morton", "f32"), ("morton", "bf16"), ("index", "bf16")):
+            if (o, mo) == (args.order, args.moments):
+                continue
+            r = guarded(f"{o} order, {mo} moments", layout_leg, o, mo)
+            variants.extend(r if isinstance(r, list) else [dict(r, order=o, moments=mo)])
+        if "morton" in layouts:
+            variants.append({"next_rows": guarded("widened rows (noise, AIU, multi-view, prune/append)",
+                                                  run_next_rows, gs, torch, layouts["morton"], cams)})
+            unf = guarded("unfused eager comparator", run_unfused, gs, torch, layouts["morton"], cams)
+            fused_ms = head["ms_per_step"] if (args.order, args.moments) == ("morton", "f32") else None
+            if "error" not in unf:
+                unf["fused_speedup"] = unf["ms_per_step"] / fused_ms if fused_ms else None
+            variants.append({"unfused_comparator": unf})
         del layouts
         torch.cuda.empty_cache()
-        print("bench: variant batched 16 scenes", file=sys.stderr, flush=True)
-        variants.append({"batched": run_batched(gs, torch)})
-        print("bench: variant MCMC-shaped 6M with relocation", file=sys.stderr, flush=True)
-        view, two = run_mcmc_both(gs, torch, cams)
-        variants.append({"mcmc_6m": view})
-        variants.append({"mcmc_6m_two_launch": two})
+        variants.append({"config1_100k": guarded("100k plain (cache-resident)", run_config1, gs, torch)})
+        variants.append({"batched": guarded("batched 16 scenes", run_batched, gs, torch)})
+        mc = guarded("MCMC-shaped 6M with relocation", run_mcmc_both, gs, torch, cams)
+        if isinstance(mc, list):
+            variants.append({"mcmc_6m": mc[0]})
+            variants.append({"mcmc_6m_two_launch": mc[1]})
+        else:
+            variants.append({"mcmc_6m": mc})
 
     traffic = measured_traffic(args.order, args.moments, args.path)
     out = {
@@ -1093,6 +1266,7 @@ def main(argv=None) -> int:
             "schedule": "view windows" if args.path == "view" else "masked windows",
             "unit": ("32 (64 on Re-State iterations)" if VIEW_UNIT == 0 else VIEW_UNIT) if args.path == "view"
                     else STEP_LAUNCH["unit"],
+            "same_state_as_two_launch": same_as_two_launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -1113,19 +1287,20 @@ def main(argv=None) -> int:
         "cpu_baseline": None,
         "variants": variants,
     }
-    print("bench: streaming ceilings", file=sys.stderr, flush=True)
-    try:
-        ceil = stream_ceilings(torch)
+    ceil = guarded("streaming ceilings", stream_ceilings, torch)
+    if "error" not in ceil:
+        ceil.pop("table")
         ceil["step_frac_of_rmw_4r3w"] = head["achieved_GBps"] / ceil["rmw_4r3w_GBps"]
-        ceil["kind"] = ("plain contiguous kernels, 16-byte non-temporal accesses, 4 in flight per thread, "
-                        "4 x 256 MiB arrays (libgsprobe)")
-    except OSError as e:                  # the probe library is context, not the measurement
-        ceil = {"error": f"libgsprobe.so not loadable: {e}"}
+        ceil["step_frac_of_rmw_4r3w_best"] = head["achieved_GBps"] / ceil["rmw_4r3w_best_GBps"]
+        ceil["kind"] = ("plain contiguous kernels over 4 x 256 MiB arrays (bench_probe); *_GBps: 16-byte "
+                        "non-temporal accesses, 4 in flight per thread, one tile per block; *_best_GBps: the "
+                        "fastest of the swept launch shapes (width, in flight, hints, grid form)")
     out["stream_ceiling"] = ceil
     out["gpu_clocks"] = gpu_clocks()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(scene, cams, order, budget_s=args.cpu_budget)
+        out["cpu_baseline"] = guarded("CPU oracle baseline", cpu_baseline, scene, cams, order,
+                                      budget_s=args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 

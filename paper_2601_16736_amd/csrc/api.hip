@@ -428,8 +428,8 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     memset(&k, 0, sizeof k);
     gs_status st = GS_OK;
     for (int v = 0; v < n_cams && st == GS_OK; ++v) {
-        char prefix[32];
-        snprintf(prefix, sizeof prefix, n_cams > 1 ? "view %d: " : "", v);
+        char prefix[32] = "";
+        if (n_cams > 1) snprintf(prefix, sizeof prefix, "view %d: ", v);
         st = to_kcamera(&cams[v], &k.c[v], prefix);
     }
     if (st != GS_OK) return st;
