@@ -366,6 +366,26 @@ gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_gro
                             int32_t reset_t, int32_t* selected, void* workspace,
                             size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): gs_relocate_reset with
+ * no workspace argument.  Same selection, results and argument rules; the
+ * workspace is instead a device array of fixed size inside the library
+ * (about 390 KB, one copy on each device the library runs on, held until the
+ * process ends), so n is limited to GS_RELOCATE_NOALLOC_MAX_N (GS_EINVAL
+ * above it; gs_relocate_reset serves larger n).  The call allocates nothing:
+ * its first call on a device looks up that device's copy (with the device
+ * current, as for any call: the stream must belong to the current device).
+ * Every call on one device shares that copy, and each call clears what it
+ * needs on the device before using it: calls that overlap on one device
+ * (on two streams, or from two host threads) race and give undefined
+ * results; calls issued one after another on one stream do not.
+ */
+#define GS_RELOCATE_NOALLOC_MAX_N ((int64_t)1 << 27)
+gs_status gs_relocate_reset_noalloc(const float* key, int64_t n, int64_t k, const gs_group* groups,
+                                    int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
+                                    int32_t reset_t, int32_t* selected, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Schedule tuner.
  * ---------------------------------------------------------------------- */

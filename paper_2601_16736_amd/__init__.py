@@ -116,6 +116,9 @@ _lib.gs_relocate_workspace_size.argtypes = [_i64]
 _lib.gs_relocate_reset.restype = _i32
 _lib.gs_relocate_reset.argtypes = [_vp, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp, _vp,
                                    _sz, _vp]
+_lib.gs_relocate_reset_noalloc.restype = _i32
+_lib.gs_relocate_reset_noalloc.argtypes = [_vp, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp,
+                                           _vp]
 _lib.gs_tune.restype = _i32
 _lib.gs_tune.argtypes = [_i64, ctypes.POINTER(_i32), _i32, ctypes.c_float, _i32, ctypes.POINTER(_i32),
                          ctypes.POINTER(_i32)]
@@ -138,7 +141,7 @@ _lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_visibility_multi", "gs_compact",
             "adamw_gs_step", "adamw_gs_step_view", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_set_resident", "gs_batch_scene_schedule",
             "gs_batch_destroy",
-            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_tune", "gs_tune_clear",
+            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_relocate_reset_noalloc", "gs_tune", "gs_tune_clear",
             "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
             "gs_prune", "gs_append"]
 
@@ -411,6 +414,20 @@ def gs_relocate_reset(key, k: int, groups: Sequence[Group], moment_dtype: int, s
     _check(_lib.gs_relocate_reset(_ptr(key), n, int(k), arr, len(groups), int(moment_dtype), _ptr(step_count),
                                   int(bool(reset_t)), _ptr(selected), _ptr(workspace), ws_bytes,
                                   _stream(stream)))
+
+
+# largest n gs_relocate_reset_noalloc serves (GS_RELOCATE_NOALLOC_MAX_N in gsopt.h)
+GS_RELOCATE_NOALLOC_MAX_N = 1 << 27
+
+
+def gs_relocate_reset_noalloc(key, k: int, groups: Sequence[Group], moment_dtype: int, step_count,
+                              reset_t: bool, selected=None, stream=None) -> None:
+    """gs_relocate_reset on the library's own fixed device workspace: no
+    allocation, n <= GS_RELOCATE_NOALLOC_MAX_N (see include/gsopt.h)."""
+    arr = _groups_c(groups)
+    n = int(key.shape[0])
+    _check(_lib.gs_relocate_reset_noalloc(_ptr(key), n, int(k), arr, len(groups), int(moment_dtype),
+                                          _ptr(step_count), int(bool(reset_t)), _ptr(selected), _stream(stream)))
 
 
 def gs_tune(n: int, dims: Sequence[int], visible_fraction: float, moment_dtype: int = GS_MOMENT_F32):

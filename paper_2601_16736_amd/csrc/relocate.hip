@@ -10,6 +10,7 @@
 // the first r keys == K in index order, writing the selected indices in
 // ascending order and zeroing their state rows.
 #include <cstring>
+#include <mutex>
 
 #include "device_common.h"
 
@@ -31,7 +32,28 @@ constexpr int kHistCopies = 8;
 constexpr int kHistStride = 1024;
 constexpr int kHistWords = 4 * kHistCopies * kHistStride;
 
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout for n keys: the select states (one aligned slot), the
+// pass histograms, then the per-block counts below K and equal to K.
+constexpr size_t workspace_bytes_for(int64_t n)
+{
+    return kAlign + align_up((size_t)kHistWords * 4) +
+           2 * align_up((size_t)((n + kRelPerBlock - 1) / kRelPerBlock) * 4);
+}
+
+constexpr size_t kScratchBytes = workspace_bytes_for(GS_RELOCATE_NOALLOC_MAX_N);
+
+}  // namespace
+}  // namespace gs
+
+// The no-allocation entry point's workspace: one copy per device, held
+// until the process ends, sized for GS_RELOCATE_NOALLOC_MAX_N keys.  Host
+// code uses its device address (scratch_address), never this name.
+static __device__ __align__(256) unsigned char scratch[gs::kScratchBytes];
+
+namespace gs {
+namespace {
 
 struct SelectState {
     uint32_t prefix;   // key bits decided so far
@@ -386,11 +408,31 @@ void launch_write(int nblocks, hipStream_t stream, const float* key, int64_t n, 
 
 }  // namespace
 
-size_t relocate_workspace_bytes(int64_t n)
+size_t relocate_workspace_bytes(int64_t n) { return workspace_bytes_for(n); }
+
+// Device address of this device's `scratch`, looked up once per device with
+// that device current (host code must not pass the array's own name, which
+// is a host-side stand-in).  nullptr and the HIP error on failure.
+constexpr int kMaxDevices = 64;
+void* scratch_address(hipError_t* err)
 {
-    const size_t nblocks = (size_t)((n + kRelPerBlock - 1) / kRelPerBlock);
-    return kAlign /* states */ + align_up(kHistWords * 4) /* pass histograms */ +
-           2 * align_up(nblocks * 4) /* per-block counts */;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        addr[dev] = p;
+    }
+    return addr[dev];
 }
 
 hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene& s, int reset_t, int32_t* selected,
@@ -429,29 +471,90 @@ extern "C" size_t gs_relocate_workspace_size(int64_t n)
     return n < 0 ? 0 : relocate_workspace_bytes(n);
 }
 
+namespace {
+
+// Host-side checks and group set-up shared by both entry points.
+gs_status relocate_prepare(const char* who, const float* key, int64_t n, int64_t k, const gs_group* groups,
+                           int32_t n_groups, int32_t moment_dtype, int32_t* step_count, int32_t reset_t,
+                           int32_t* selected, KScene* s, bool* empty)
+{
+    char msg[160];
+    *empty = false;
+    if (n < 0 || n >= ((int64_t)1 << 31)) {
+        snprintf(msg, sizeof msg, "%s: n must be in [0, 2^31)", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (k < 0 || k > n) {
+        snprintf(msg, sizeof msg, "%s: k must be in [0, n]", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (moment_dtype != GS_MOMENT_F32 && moment_dtype != GS_MOMENT_BF16) {
+        snprintf(msg, sizeof msg, "%s: unknown moment_dtype", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (n == 0) {                      // nothing to select: no other argument is read
+        *empty = true;
+        return GS_OK;
+    }
+    if (key == nullptr) {
+        snprintf(msg, sizeof msg, "%s: key is required", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if ((uintptr_t)key % 4 || (uintptr_t)selected % 4 || (uintptr_t)step_count % 4) {
+        snprintf(msg, sizeof msg, "%s: misaligned key, selected or step_count", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (reset_t && step_count == nullptr) {
+        snprintf(msg, sizeof msg, "%s: reset_t needs step_count", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    gs_step_config cfg;
+    memset(&cfg, 0, sizeof cfg);
+    cfg.reg_norm = 1.0;
+    memset(s, 0, sizeof *s);
+    snprintf(msg, sizeof msg, "%s: ", who);
+    const gs_status st = build_groups(groups, n_groups, n, moment_dtype, &cfg, s, msg);
+    if (st != GS_OK) return st;
+    s->t = step_count;
+    return GS_OK;
+}
+
+}  // namespace
+
 extern "C" gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_group* groups,
                                        int32_t n_groups, int32_t moment_dtype, int32_t* step_count, int32_t reset_t,
                                        int32_t* selected, void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
     clear_error();
-    if (n < 0 || n >= ((int64_t)1 << 31)) return set_error(GS_EINVAL, "gs_relocate_reset: n must be in [0, 2^31)");
-    if (k < 0 || k > n) return set_error(GS_EINVAL, "gs_relocate_reset: k must be in [0, n]");
-    if (moment_dtype != GS_MOMENT_F32 && moment_dtype != GS_MOMENT_BF16)
-        return set_error(GS_EINVAL, "gs_relocate_reset: unknown moment_dtype");
-    if (n == 0) return GS_OK;
-    if (key == nullptr || workspace == nullptr) return set_error(GS_EINVAL, "gs_relocate_reset: key and workspace are required");
-    if ((uintptr_t)key % 4 || (uintptr_t)workspace % kAlign || (uintptr_t)selected % 4 || (uintptr_t)step_count % 4)
-        return set_error(GS_EINVAL, "gs_relocate_reset: misaligned pointer (workspace needs 256 bytes)");
-    if (workspace_bytes < relocate_workspace_bytes(n)) return set_error(GS_EINVAL, "gs_relocate_reset: workspace too small");
-    if (reset_t && step_count == nullptr) return set_error(GS_EINVAL, "gs_relocate_reset: reset_t needs step_count");
-    gs_step_config cfg;
-    memset(&cfg, 0, sizeof cfg);
-    cfg.reg_norm = 1.0;
     KScene s;
-    memset(&s, 0, sizeof s);
-    const gs_status st = build_groups(groups, n_groups, n, moment_dtype, &cfg, &s, "gs_relocate_reset: ");
-    if (st != GS_OK) return st;
-    s.t = step_count;
+    bool empty = false;
+    gs_status st = relocate_prepare("gs_relocate_reset", key, n, k, groups, n_groups, moment_dtype, step_count,
+                                    reset_t, selected, &s, &empty);
+    if (st != GS_OK || empty) return st;
+    if (workspace == nullptr) return set_error(GS_EINVAL, "gs_relocate_reset: workspace is required");
+    if ((uintptr_t)workspace % kAlign)
+        return set_error(GS_EINVAL, "gs_relocate_reset: misaligned workspace (needs 256 bytes)");
+    if (workspace_bytes < relocate_workspace_bytes(n)) return set_error(GS_EINVAL, "gs_relocate_reset: workspace too small");
     const hipError_t e = launch_relocate(key, n, k, s, reset_t, selected, workspace, stream);
+    return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
+}
+
+extern "C" gs_status gs_relocate_reset_noalloc(const float* key, int64_t n, int64_t k, const gs_group* groups,
+                                               int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
+                                               int32_t reset_t, int32_t* selected, hipStream_t stream)
+{
+    clear_error();
+    if (n > GS_RELOCATE_NOALLOC_MAX_N)
+        return set_error(GS_EINVAL, "gs_relocate_reset_noalloc: n exceeds GS_RELOCATE_NOALLOC_MAX_N "
+                                    "(use gs_relocate_reset with a workspace)");
+    KScene s;
+    bool empty = false;
+    gs_status st = relocate_prepare("gs_relocate_reset_noalloc", key, n, k, groups, n_groups, moment_dtype,
+                                    step_count, reset_t, selected, &s, &empty);
+    if (st != GS_OK || empty) return st;
+    hipError_t e = hipSuccess;
+    void* ws = scratch_address(&e);
+    if (ws == nullptr) return set_error(GS_EHIP, hipGetErrorString(e));
+    e = launch_relocate(key, n, k, s, reset_t, selected, ws, stream);
     return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
 }

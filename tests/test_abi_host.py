@@ -256,3 +256,53 @@ def test_append_rejects_bad_arguments():
     assert app(t=FAKE + 2).status == gs.GS_EINVAL
     assert app(groups=[_group(param=_Fake(FAKE, (14, 3)), exp_avg=FAKE + 1)]).status == gs.GS_EINVAL
     assert app(groups=[]).status == gs.GS_EINVAL
+
+
+def test_relocate_entry_points_reject_bad_arguments():
+    """Both relocation entry points validate the same arguments before any
+    launch; the no-allocation one also refuses n above its fixed maximum."""
+    ws = _Fake(FAKE + (1 << 24), (1 << 20,))
+    ws.numel, ws.element_size = (lambda: 1 << 20), (lambda: 1)
+
+    def with_ws(n=10, k=4, dtype=0, key=FAKE + 65536, t=FAKE + 131072, sel=FAKE + 196608, reset_t=True,
+                groups=None, workspace=ws):
+        groups = [_group(param=_Fake(FAKE, (n, 3)))] if groups is None else groups
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_relocate_reset(_Fake(key, (n,)), k, groups, dtype, t, reset_t, workspace, selected=sel, stream=0)
+        return e.value.status
+
+    def noalloc(n=10, k=4, dtype=0, key=FAKE + 65536, t=FAKE + 131072, sel=FAKE + 196608, reset_t=True,
+                groups=None):
+        groups = [_group(param=_Fake(FAKE, (n, 3)))] if groups is None else groups
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_relocate_reset_noalloc(_Fake(key, (n,)), k, groups, dtype, t, reset_t, selected=sel, stream=0)
+        return e.value.status
+
+    for call in (with_ws, noalloc):
+        assert call(n=-1) == gs.GS_EINVAL
+        assert call(k=-1) == gs.GS_EINVAL
+        assert call(k=11) == gs.GS_EINVAL
+        assert call(dtype=2) == gs.GS_EINVAL
+        assert call(key=0) == gs.GS_EINVAL
+        assert call(key=FAKE + 2) == gs.GS_EINVAL
+        assert call(sel=FAKE + 1) == gs.GS_EINVAL
+        assert call(t=0) == gs.GS_EINVAL                          # reset_t needs step_count
+        assert call(groups=[_group(param=_Fake(FAKE, (10, 3)), exp_avg=FAKE + 1)]) == gs.GS_EINVAL
+    assert with_ws(n=2**31) == gs.GS_EINVAL
+    null_ws = _Fake(0, (1 << 20,))
+    null_ws.numel, null_ws.element_size = (lambda: 1 << 20), (lambda: 1)
+    assert with_ws(workspace=null_ws) == gs.GS_EINVAL
+    odd_ws = _Fake(FAKE + 64, (1 << 20,))
+    odd_ws.numel, odd_ws.element_size = (lambda: 1 << 20), (lambda: 1)
+    assert with_ws(workspace=odd_ws) == gs.GS_EINVAL              # workspace needs 256-byte alignment
+    small = _Fake(FAKE + (1 << 24), (8,))
+    small.numel, small.element_size = (lambda: 8), (lambda: 1)
+    assert with_ws(workspace=small) == gs.GS_EINVAL
+    assert noalloc(n=gs.GS_RELOCATE_NOALLOC_MAX_N + 1) == gs.GS_EINVAL
+    assert "GS_RELOCATE_NOALLOC_MAX_N" in gs.last_error()
+    # the binding's constant is the header's
+    text = open(HEADER).read()
+    assert re.search(r"#define GS_RELOCATE_NOALLOC_MAX_N \(\(int64_t\)1 << 27\)", text)
+    assert gs.GS_RELOCATE_NOALLOC_MAX_N == 1 << 27
+    # n = 0 is a no-op that reads no other argument
+    gs.gs_relocate_reset_noalloc(_Fake(0, (0,)), 0, [], 0, 0, False, stream=0)
