@@ -250,7 +250,7 @@ PROBE_SHAPES = [(w, it, ntl, nts, b) for w in (16, 8) for it in (2, 4, 8, 16) fo
                 for b in (0, 1024, 2048)]
 
 
-def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None) -> dict:
+def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None, stagger: int = 0) -> dict:
     """Bandwidth of plain contiguous kernels on this device (bench_probe):
     the step's 4-read / 3-write mix over four arrays of `nbytes`, a copy and
     a read, each timed with HIP events over `reps` launches after 3 untimed
@@ -258,12 +258,22 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None)
     flight per thread, non-temporal hints on loads / stores, one-shot or
     resident grid).  Reports the fixed default shape and the best shape of
     each mix.  Four arrays of 256 MiB exceed the 256 MB Infinity Cache, so
-    every pass streams from HBM."""
+    every pass streams from HBM.  stagger = 0: four separate allocations;
+    > 0: one allocation holding array k at offset k * (nbytes + stagger),
+    so the arrays' element i sit at different offsets modulo any power of
+    two up to stagger's lowest set bit."""
     import bench_probe
     lib = bench_probe.load()
     vp = __import__("ctypes").c_void_p
     dev = torch.device(DEVICE)
-    arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
+    if stagger > 0:
+        if stagger % 16:
+            raise ValueError("stagger must be a multiple of 16 bytes")
+        pitch = (nbytes + stagger) // 4
+        whole = torch.rand(4 * pitch, device=dev)
+        arrs = [whole[k * pitch:k * pitch + nbytes // 4] for k in range(4)]
+    else:
+        arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
     sink = torch.zeros(4, device=dev)
     n16 = nbytes // 16
     stream = torch.cuda.current_stream()
@@ -306,6 +316,7 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None)
         out[f"{mix}_best_shape"] = best
     out["shapes_timed"] = len(shapes)
     out["default_shape"] = dkey
+    out["stagger"] = stagger
     out["table"] = table
     del arrs, sink
     torch.cuda.empty_cache()
@@ -349,6 +360,33 @@ class SceneOnDevice:
             self.grads = [gs.apply_spatial_order(sets, perm) for sets in self.grads]
             del ws, perm
         torch.cuda.synchronize()
+
+
+def device_warmup(gs, torch, sd: SceneOnDevice, cams, seconds: float = 1.0) -> int:
+    """Brings the device to its working clocks before anything is timed: the
+    fused view step on a scratch copy of the scene's state, stepped through
+    the camera rig until `seconds` of wall time have passed.  Nothing it
+    computes is kept.  Returns the number of steps taken."""
+    import synth
+    dev = torch.device(DEVICE)
+    groups = [gs.Group(p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                       dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+              for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
+    t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    stream = torch.cuda.current_stream()
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(50):
+            cfg = gs.StepConfig(reg_norm=REG_NORM, seed=7, iteration=k, unit=VIEW_UNIT)
+            gs.adamw_gs_step_view(groups, N_PRIMS, t, cfg, groups[0].param, gcams[k % len(gcams)], stream=stream)
+            k += 1
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            break
+    del groups, t
+    return k
 
 
 def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: int, warmup: int,
@@ -1085,8 +1123,11 @@ def main(argv=None) -> int:
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--device-warmup", type=float, default=1.0,
+                    help="seconds of discarded fused steps before anything is timed (device clocks)")
     ap.add_argument("--probe-sweep", action="store_true",
-                    help="only time the streaming probes over every launch shape (one JSON line with the table)")
+                    help="only time the streaming probes over every launch shape, for separate and for staggered "
+                         "arrays (one JSON line with the table per array layout)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 10 times (counter calibration)")
     ap.add_argument("--mcmc-only", action="store_true",
@@ -1110,7 +1151,8 @@ def main(argv=None) -> int:
         return calibrate_copy()
     if args.probe_sweep:
         import torch
-        print(json.dumps(stream_ceilings(torch)), flush=True)
+        for stagger in (0, 4096 + 256, 1 << 20):
+            print(json.dumps(stream_ceilings(torch, stagger=stagger)), flush=True)
         return 0
     if args.batched_only:
         import torch
@@ -1167,6 +1209,8 @@ def main(argv=None) -> int:
     order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
 
     layouts = {args.order: SceneOnDevice(gs, torch, scene, args.order)}
+    print(f"bench: device warm-up ({args.device_warmup:.1f} s of discarded steps)", file=sys.stderr, flush=True)
+    warm_steps = device_warmup(gs, torch, layouts[args.order], cams, seconds=args.device_warmup)
     # the two-launch path (gs_visibility, then the masked step) always runs
     # first: it is a variant line, and its per-step visible counts are the
     # fused path's too, since both produce the same bits (checked below)
@@ -1267,6 +1311,7 @@ def main(argv=None) -> int:
             "unit": ("32 (64 on Re-State iterations)" if VIEW_UNIT == 0 else VIEW_UNIT) if args.path == "view"
                     else STEP_LAUNCH["unit"],
             "same_state_as_two_launch": same_as_two_launch,
+            "device_warmup_steps": warm_steps,
         },
         "roofline": {
             "bound": "hbm",
