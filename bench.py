@@ -70,6 +70,7 @@ BYTES_PER_PRIMITIVE = {"two_launch": 1, "view": 12}
 LAMBDA_O, LAMBDA_S, CLIP, REG_NORM = 1e-3, 1e-5, 10.0, 1e5
 RSR_EVERY, RSR_P, RSR_A1, RSR_A2 = 100, 0.05, 0.2, 0.04
 N_GRAD_SETS = 4
+GS_F32, GS_BF16 = 0, 1               # moment dtypes (gs_moment_dtype)
 # primitives per wave window in the fused view step: 0 = the library's
 # default, 32 on plain steps and 64 on Re-State iterations
 VIEW_UNIT = 0
@@ -246,7 +247,8 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 10) -> int:
 
 
 PROBE_DEFAULT = (16, 4, 1, 1, 0)          # width, items, nt_load, nt_store, blocks
-PROBE_SHAPES = [(w, it, ntl, nts, b) for w in (16, 8) for it in (2, 4, 8, 16) for ntl in (1, 0) for nts in (1, 0)
+# nt_load 2: the hint only on the loads of arrays that are written back
+PROBE_SHAPES = [(w, it, ntl, nts, b) for w in (16, 8) for it in (2, 4, 8, 16) for ntl in (1, 0, 2) for nts in (1, 0)
                 for b in (0, 1024, 2048)]
 
 
@@ -302,6 +304,8 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None,
         key = f"w{w}_i{it}_ntl{ntl}_nts{nts}_b{b}"
         table["rmw_4r3w"][key] = 7 * nbytes / timed(
             lambda: lib.gsprobe_rmw_4r3w_cfg(ptr[0], ptr[1], ptr[2], ptr[3], n16, w, it, ntl, nts, b, sp)) / 1e9
+        if ntl == 2:                    # copy and read write back nothing they read
+            continue
         table["copy"][key] = 2 * nbytes / timed(
             lambda: lib.gsprobe_copy_cfg(ptr[0], ptr[1], n16, w, it, ntl, nts, b, sp)) / 1e9
         if nts == 1:                    # a read has no stores: one entry per load hint
@@ -899,6 +903,72 @@ def run_sweep(gs, torch, steps: int = 100, warmup: int = 10, only_n: int = 0) ->
     return out
 
 
+def run_profile_set(gs, torch, reps: int = 10) -> dict:
+    """A short, fixed sequence of launches for counter runs (rocprofv3
+    --pmc): on the 3M scene (means U[-10, 10]^3 drawn on the device, Morton
+    order, other attributes N(0, 1), z_far 17.5) `reps` fused view steps with
+    FP32 moments, `reps` with BF16 moments, `reps` / 2 dense steps (every
+    primitive visible, windows of 64) with FP32 moments; then the streaming
+    probes' 4-read / 3-write mix in its default and best swept shapes and the
+    copy in its best shape, `reps` launches each over 4 x 256 MiB.  Each
+    kernel is told apart by its name (template arguments) in the trace."""
+    import ctypes
+
+    import bench_probe
+    import synth
+    dev = torch.device(DEVICE)
+    n = N_PRIMS
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(n)
+    means = torch.rand((n, 3), generator=gen, device=dev) * 20.0 - 10.0
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(gs.gs_spatial_order_workspace_size(n), dtype=torch.uint8, device=dev)
+    gs.gs_spatial_order(means, perm, ws)
+    means = gs.apply_spatial_order([means], perm)[0]
+    del perm, ws
+    params = [means] + [torch.randn((n, d), generator=gen, device=dev) for _, d, _, _ in synth.GROUPS_59[1:]]
+    grads = [torch.randn((n, d), generator=gen, device=dev) * 1e-3 for _, d, _, _ in synth.GROUPS_59]
+    cams = synth.camera_rig(z_far=17.5)
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    order = synth.camera_order(len(cams), 4 * reps, seed=1)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for label, mdt, mom, sched, count in (("view_f32", torch.float32, GS_F32, None, reps),
+                                          ("view_bf16", torch.bfloat16, GS_BF16, None, reps),
+                                          ("dense_f32", torch.float32, GS_F32, 3, max(reps // 2, 1))):
+        groups = [gs.Group(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev),
+                           torch.zeros(p.shape, dtype=mdt, device=dev), lr, dar_kind=dar,
+                           dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+                  for (name, d, lr, dar), p, g in zip(synth.GROUPS_59, params, grads)]
+        t = torch.zeros(n, dtype=torch.int32, device=dev)
+        for k in range(count):
+            cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k + 1, moment_dtype=mom,
+                                **({} if sched is None else {"schedule": sched}))
+            if sched is None:
+                gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, gcams[order[k % len(order)]],
+                                      stream=stream)
+            else:
+                gs.adamw_gs_step(groups, n, t, cfg, stream=stream)
+        torch.cuda.synchronize()
+        out[label] = count
+        del groups, t
+    del params, grads, means
+    torch.cuda.empty_cache()
+    lib = bench_probe.load()
+    nbytes = 256 << 20
+    arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
+    ptr = [a.data_ptr() for a in arrs]
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    for (w, it, ntl, nts) in ((16, 4, 1, 1), (8, 4, 1, 1)):
+        for _ in range(reps):
+            lib.gsprobe_rmw_4r3w_cfg(ptr[0], ptr[1], ptr[2], ptr[3], nbytes // 16, w, it, ntl, nts, 0, sp)
+    for _ in range(reps):
+        lib.gsprobe_copy_cfg(ptr[0], ptr[1], nbytes // 16, 8, 4, 0, 1, 0, sp)
+    torch.cuda.synchronize()
+    out["probe"] = reps
+    return out
+
+
 def same_state(torch, a, b) -> bool:
     """Bit equality of two (groups, step counts) end states."""
     (ga, ta), (gb, tb) = a, b
@@ -1125,6 +1195,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--device-warmup", type=float, default=1.0,
                     help="seconds of discarded fused steps before anything is timed (device clocks)")
+    ap.add_argument("--profile-set", action="store_true",
+                    help="only a short fixed sequence of step and probe launches, for counter runs")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="only time the streaming probes over every launch shape, for separate and for staggered "
                          "arrays (one JSON line with the table per array layout)")
@@ -1149,6 +1221,11 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.profile_set:
+        import torch
+        import paper_2601_16736_amd as gs
+        print(json.dumps(run_profile_set(gs, torch)), flush=True)
+        return 0
     if args.probe_sweep:
         import torch
         for stagger in (0, 4096 + 256, 1 << 20):

@@ -15,7 +15,10 @@
 //   width     bytes per access: 8 or 16;
 //   items     accesses in flight per thread per array: 2, 4, 8 or 16 (all
 //             loads of a tile are issued before any store);
-//   nt_load / nt_store   the non-temporal hint on loads / stores;
+//   nt_load / nt_store   the non-temporal hint on loads / stores; nt_load = 2
+//             hints only the loads of arrays that are written back (the
+//             4-read / 3-write mix's parameter and moments; its gradient
+//             is loaded plainly);
 //   blocks    0: one tile per block (the grid covers the arrays once);
 //             > 0: that many blocks, each striding over the tiles.
 // A tile is 256 threads x items accesses, 256 accesses apart per item, so
@@ -44,7 +47,8 @@ __device__ __forceinline__ void st(T x, T* p)
     else *p = x;
 }
 
-template <typename T, int ITEMS, bool NTL, bool NTS>
+// NTL: 0 none, 1 every load, 2 the loads of the arrays written back
+template <typename T, int ITEMS, int NTL, bool NTS>
 __global__ __launch_bounds__(kThreads) void rmw_4r3w_kernel(T* p, const T* g, T* m, T* v, int64_t n, int64_t tiles)
 {
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -53,10 +57,10 @@ __global__ __launch_bounds__(kThreads) void rmw_4r3w_kernel(T* p, const T* g, T*
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             const int64_t i = min(base + u * kThreads, n - 1);
-            a[u] = ld<NTL>(p + i);
-            b[u] = ld<NTL>(g + i);
-            c[u] = ld<NTL>(m + i);
-            d[u] = ld<NTL>(v + i);
+            a[u] = ld<NTL != 0>(p + i);
+            b[u] = ld<NTL == 1>(g + i);
+            c[u] = ld<NTL != 0>(m + i);
+            d[u] = ld<NTL != 0>(v + i);
         }
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
@@ -71,14 +75,14 @@ __global__ __launch_bounds__(kThreads) void rmw_4r3w_kernel(T* p, const T* g, T*
     }
 }
 
-template <typename T, int ITEMS, bool NTL, bool NTS>
+template <typename T, int ITEMS, int NTL, bool NTS>
 __global__ __launch_bounds__(kThreads) void copy_kernel(T* dst, const T* src, int64_t n, int64_t tiles)
 {
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kThreads * ITEMS + threadIdx.x;
         T a[ITEMS];
 #pragma unroll
-        for (int u = 0; u < ITEMS; ++u) a[u] = ld<NTL>(src + min(base + u * kThreads, n - 1));
+        for (int u = 0; u < ITEMS; ++u) a[u] = ld<NTL == 1>(src + min(base + u * kThreads, n - 1));
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             const int64_t i = base + u * kThreads;
@@ -89,14 +93,14 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(T* dst, const T* src, in
 
 // Sums each thread's elements; one lane writes only if the sum equals a
 // value it cannot take for the probe's data, so the loads are kept.
-template <typename T, int ITEMS, bool NTL, bool NTS>
+template <typename T, int ITEMS, int NTL, bool NTS>
 __global__ __launch_bounds__(kThreads) void read_kernel(const T* src, int64_t n, int64_t tiles, float* sink)
 {
     T s = {};
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         const int64_t base = tile * kThreads * ITEMS + threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < ITEMS; ++u) s += ld<NTL>(src + min(base + u * kThreads, n - 1));
+        for (int u = 0; u < ITEMS; ++u) s += ld<NTL == 1>(src + min(base + u * kThreads, n - 1));
     }
     if (s.x == -1.0e30f) sink[0] = s.y;
 }
@@ -112,7 +116,7 @@ struct Args {
     int blocks;
 };
 
-template <typename T, int ITEMS, bool NTL, bool NTS>
+template <typename T, int ITEMS, int NTL, bool NTS>
 int launch(Mix mix, const Args& x, hipStream_t stream)
 {
     constexpr int64_t per16 = 16 / sizeof(T);
@@ -136,10 +140,9 @@ int launch(Mix mix, const Args& x, hipStream_t stream)
 template <typename T, int ITEMS>
 int by_hint(Mix mix, const Args& x, int ntl, int nts, hipStream_t s)
 {
-    if (ntl && nts) return launch<T, ITEMS, true, true>(mix, x, s);
-    if (ntl) return launch<T, ITEMS, true, false>(mix, x, s);
-    if (nts) return launch<T, ITEMS, false, true>(mix, x, s);
-    return launch<T, ITEMS, false, false>(mix, x, s);
+    if (ntl == 2) return nts ? launch<T, ITEMS, 2, true>(mix, x, s) : launch<T, ITEMS, 2, false>(mix, x, s);
+    if (ntl == 1) return nts ? launch<T, ITEMS, 1, true>(mix, x, s) : launch<T, ITEMS, 1, false>(mix, x, s);
+    return nts ? launch<T, ITEMS, 0, true>(mix, x, s) : launch<T, ITEMS, 0, false>(mix, x, s);
 }
 
 template <typename T>
@@ -163,9 +166,10 @@ int dispatch(Mix mix, const Args& x, int width, int items, int ntl, int nts, hip
 
 bool bad(const void* p) { return p == nullptr || (uintptr_t)p % 16 != 0; }
 bool bad_n(int64_t n16) { return n16 < 1 || n16 > ((int64_t)1 << 31); }
-bool bad_shape(int width, int items, int blocks)
+bool bad_shape(int width, int items, int blocks, int ntl)
 {
-    return (width != 8 && width != 16) || (items != 2 && items != 4 && items != 8 && items != 16) || blocks < 0;
+    return (width != 8 && width != 16) || (items != 2 && items != 4 && items != 8 && items != 16) || blocks < 0 ||
+           ntl < 0 || ntl > 2;
 }
 
 }  // namespace
@@ -178,14 +182,14 @@ bool bad_shape(int width, int items, int blocks)
 extern "C" int gsprobe_rmw_4r3w_cfg(void* p, const void* g, void* m, void* v, int64_t n16, int width, int items,
                                     int nt_load, int nt_store, int blocks, hipStream_t stream)
 {
-    if (bad(p) || bad(g) || bad(m) || bad(v) || bad_n(n16) || bad_shape(width, items, blocks)) return -1;
+    if (bad(p) || bad(g) || bad(m) || bad(v) || bad_n(n16) || bad_shape(width, items, blocks, nt_load)) return -1;
     return dispatch(kRmw, Args{p, const_cast<void*>(g), m, v, n16, blocks}, width, items, nt_load, nt_store, stream);
 }
 
 extern "C" int gsprobe_copy_cfg(void* dst, const void* src, int64_t n16, int width, int items, int nt_load,
                                 int nt_store, int blocks, hipStream_t stream)
 {
-    if (bad(dst) || bad(src) || bad_n(n16) || bad_shape(width, items, blocks)) return -1;
+    if (bad(dst) || bad(src) || bad_n(n16) || bad_shape(width, items, blocks, nt_load)) return -1;
     return dispatch(kCopy, Args{dst, const_cast<void*>(src), nullptr, nullptr, n16, blocks}, width, items, nt_load,
                     nt_store, stream);
 }
@@ -193,7 +197,7 @@ extern "C" int gsprobe_copy_cfg(void* dst, const void* src, int64_t n16, int wid
 extern "C" int gsprobe_read_cfg(const void* src, int64_t n16, float* sink, int width, int items, int nt_load,
                                 int blocks, hipStream_t stream)
 {
-    if (bad(src) || sink == nullptr || bad_n(n16) || bad_shape(width, items, blocks)) return -1;
+    if (bad(src) || sink == nullptr || bad_n(n16) || bad_shape(width, items, blocks, nt_load)) return -1;
     return dispatch(kRead, Args{const_cast<void*>(src), sink, nullptr, nullptr, n16, blocks}, width, items, nt_load,
                     0, stream);
 }
