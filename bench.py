@@ -321,6 +321,7 @@ def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None,
     out["shapes_timed"] = len(shapes)
     out["default_shape"] = dkey
     out["stagger"] = stagger
+    out["array_bytes"] = nbytes
     out["table"] = table
     del arrs, sink
     torch.cuda.empty_cache()
@@ -979,15 +980,27 @@ def same_state(torch, a, b) -> bool:
         and torch.equal(bits(x.exp_avg_sq), bits(y.exp_avg_sq)) for x, y in zip(ga, gb))
 
 
+# The packed layout of the batched workload: the five attribute groups as
+# column ranges of one [n][64] array per role (attributes, gradients, each
+# moment), 16-byte aligned where their rows allow vector access.
+PACKED_WIDTH = 64
+PACKED_COLUMNS = {"sh": 0, "quats": 48, "means": 52, "scales": 55, "opacity": 58}
+
+
 def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
-                forms=("batched_bf16", "batched_bf16_resident", "per_scene_bf16", "per_scene_f32")):
+                forms=("batched_bf16", "batched_bf16_packed", "batched_bf16_resident", "per_scene_bf16",
+                       "per_scene_f32")):
     """Many-scene workload: 16 scenes with sizes log-uniform in [2e5, 4e6] and
     visible ratios U[0.02, 0.60] (Bernoulli visibility, 8 pre-drawn masks per
     scene used in turn), 59 attributes each.  Times three forms of the same
     steps: the BF16-moment plan (one persistent launch per step from a HIP
     graph, schedules picked by the tuner; one plan per mask set), and
-    per-scene adamw_gs_step calls with FP32 and with BF16 moments.  Every
-    form includes the compaction of the compacted scenes' masks."""
+    per-scene adamw_gs_step calls with FP32 and with BF16 moments.  The
+    "packed" form keeps each scene's groups as column ranges of one [n][64]
+    array per role (PACKED_COLUMNS), so that an isolated visible primitive
+    reads and writes whole 128-byte lines; its algorithmic bytes are the same
+    (the 5 padding floats per row are not counted).  Every form includes
+    the compaction of the compacted scenes' masks."""
     import synth
     dev = torch.device(DEVICE)
     sizes, ratios = synth.batch_scene_sizes(16, *BATCH_SIZE_RANGE, seed=0)
@@ -1006,17 +1019,33 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
             cnt=[torch.zeros(1, dtype=torch.int32, device=dev) for _ in range(n_masks)]))
     stream = torch.cuda.current_stream()
 
-    def make_groups(sc, mdt):
-        return [gs.Group(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev),
-                         torch.zeros(p.shape, dtype=mdt, device=dev), lr, dar_kind=dar,
-                         dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
-                for (name, d, lr, dar), p, g in zip(synth.GROUPS_59, sc["params"], sc["grads"])]
+    def make_groups(sc, mdt, packed=False):
+        lam = {1: LAMBDA_O, 2: LAMBDA_S}
+        if not packed:
+            return [gs.Group(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev),
+                             torch.zeros(p.shape, dtype=mdt, device=dev), lr, dar_kind=dar,
+                             dar_lambda=lam.get(dar, 0.0), dar_clip=CLIP)
+                    for (name, d, lr, dar), p, g in zip(synth.GROUPS_59, sc["params"], sc["grads"])]
+        # one [n][64] array per role: each primitive's state fills whole lines
+        n = sc["n"]
+        pk = {"p": torch.zeros((n, PACKED_WIDTH), device=dev), "g": torch.zeros((n, PACKED_WIDTH), device=dev),
+              "m": torch.zeros((n, PACKED_WIDTH), dtype=mdt, device=dev),
+              "v": torch.zeros((n, PACKED_WIDTH), dtype=mdt, device=dev)}
+        out = []
+        for (name, d, lr, dar), p, g in zip(synth.GROUPS_59, sc["params"], sc["grads"]):
+            c = PACKED_COLUMNS[name]
+            pk["p"][:, c:c + d] = p
+            pk["g"][:, c:c + d] = g
+            out.append(gs.Group(pk["p"][:, c:c + d], pk["g"][:, c:c + d], pk["m"][:, c:c + d], pk["v"][:, c:c + d],
+                                lr, dar_kind=dar, dar_lambda=lam.get(dar, 0.0), dar_clip=CLIP))
+        return out
 
     def timed(form):
         bf16 = form != "per_scene_f32"
         mdt = torch.bfloat16 if bf16 else torch.float32
         mom = gs.GS_MOMENT_BF16 if bf16 else gs.GS_MOMENT_F32
-        state = [dict(groups=make_groups(sc, mdt), t=torch.zeros(sc["n"], dtype=torch.int32, device=dev))
+        packed = form.endswith("packed")
+        state = [dict(groups=make_groups(sc, mdt, packed), t=torch.zeros(sc["n"], dtype=torch.int32, device=dev))
                  for sc in scenes]
         plans = []
         if form.startswith("batched_bf16"):
@@ -1195,6 +1224,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--device-warmup", type=float, default=1.0,
                     help="seconds of discarded fused steps before anything is timed (device clocks)")
+    ap.add_argument("--probe-mib", type=int, default=256,
+                    help="with --probe-sweep: MiB per probe array (4 arrays; the Infinity Cache holds 256 MB)")
     ap.add_argument("--profile-set", action="store_true",
                     help="only a short fixed sequence of step and probe launches, for counter runs")
     ap.add_argument("--probe-sweep", action="store_true",
@@ -1216,7 +1247,8 @@ def main(argv=None) -> int:
                     help="only run the 16-scene batched workload (for profiling)")
     ap.add_argument("--batched-steps", type=int, default=300,
                     help="timed steps of the batched workload (default 300)")
-    ap.add_argument("--batched-forms", default="batched_bf16,batched_bf16_resident,per_scene_bf16,per_scene_f32",
+    ap.add_argument("--batched-forms",
+                    default="batched_bf16,batched_bf16_packed,batched_bf16_resident,per_scene_bf16,per_scene_f32",
                     help="comma-separated forms of the batched workload to time")
     args = ap.parse_args(argv)
     if args.calibrate_copy:
@@ -1228,8 +1260,9 @@ def main(argv=None) -> int:
         return 0
     if args.probe_sweep:
         import torch
+        nbytes = args.probe_mib << 20
         for stagger in (0, 4096 + 256, 1 << 20):
-            print(json.dumps(stream_ceilings(torch, stagger=stagger)), flush=True)
+            print(json.dumps(stream_ceilings(torch, nbytes=nbytes, stagger=stagger)), flush=True)
         return 0
     if args.batched_only:
         import torch

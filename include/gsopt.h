@@ -28,9 +28,21 @@
  *   - NaN and Inf propagate per element; nothing is clamped or "repaired".
  *   - Indices are int32: n must be below 2^31.
  *   - Attribute groups are row-major [n][dim] (the 3DGS convention of one
- *     tensor per attribute group).  Rows of one group are updated
- *     independently, so groups may be views into one packed buffer as long
- *     as no two groups overlap.
+ *     tensor per attribute group), or, with gs_group.row_stride, column
+ *     ranges of wider row-major arrays: several groups may then share one
+ *     packed [n][row_stride] array per role (attributes, gradients, each
+ *     moment), so that all of a primitive's state sits in one line-aligned
+ *     row.  Rows of one group are updated independently; no two groups may
+ *     overlap.  When every group of a scene lies in the same packed arrays
+ *     (one row stride, a power of two from 4 to 256, each group at the same
+ *     column in the attribute, gradient and both moment arrays, row starts
+ *     16-byte aligned for the attributes and 4-element aligned for the
+ *     moments) the step takes each visible row in one pass, and writes whole
+ *     rows: the columns no group covers are read and written back with the
+ *     bits they held, so nothing else may write them during a step.
+ *   - A `means` argument is [n][3] FP32 with rows means_stride elements
+ *     apart (0 = 3), so the means may be the mean group's columns of a
+ *     packed array.
  */
 #ifndef GSOPT_H
 #define GSOPT_H
@@ -44,7 +56,7 @@
 extern "C" {
 #endif
 
-#define GSOPT_VERSION 1
+#define GSOPT_VERSION 2
 #define GS_MAX_GROUPS 8
 
 typedef enum {
@@ -86,7 +98,8 @@ typedef struct {
 } gs_camera;
 
 /*
- * means   [n][3] FP32, 4-byte aligned.
+ * means   [n][3] FP32, 4-byte aligned, rows means_stride elements apart
+ *         (0 = 3; otherwise >= 3).
  * radius  [n] FP32 world-space bounding radius per primitive, or NULL.
  * mask    [n] uint8 out (1 visible, 0 not), or NULL.
  * vis_idx [n] int32 out: indices of the visible primitives, or NULL.  The
@@ -96,7 +109,7 @@ typedef struct {
  *         when vis_idx != NULL.  It is overwritten, not accumulated.
  * At least one of mask and vis_idx must be non-NULL.
  */
-gs_status gs_visibility(const float* means, const float* radius, int64_t n,
+gs_status gs_visibility(const float* means, int64_t means_stride, const float* radius, int64_t n,
                         const gs_camera* cam, uint8_t* mask, int32_t* vis_idx,
                         int32_t* vis_count, hipStream_t stream);
 
@@ -110,7 +123,7 @@ gs_status gs_visibility(const float* means, const float* radius, int64_t n,
  * vis_idx / vis_count: the union's indices, as for gs_visibility, or NULL.
  * At least one output must be non-NULL.  cams is a host array.
  */
-gs_status gs_visibility_multi(const float* means, const float* radius, int64_t n,
+gs_status gs_visibility_multi(const float* means, int64_t means_stride, const float* radius, int64_t n,
                               const gs_camera* cams, int32_t n_cams, uint8_t* mask,
                               uint32_t* view_bits, int32_t* vis_idx, int32_t* vis_count,
                               hipStream_t stream);
@@ -154,7 +167,9 @@ typedef struct {
     int32_t dim;             /* >= 1 */
     int32_t dar_kind;        /* gs_dar_kind */
     int32_t reg_mode;        /* gs_reg_mode (ignored when dar_kind == GS_DAR_NONE) */
-    int32_t reserved;        /* must be 0 */
+    int32_t row_stride;      /* elements from the start of one row to the next, the same in param, grad,
+                                exp_avg and exp_avg_sq: 0 = dim (contiguous rows), else >= dim (the group
+                                is dim columns of [n][row_stride] arrays) */
     double lr;               /* eta of this attribute group, finite */
     double dar_lambda;       /* lambda_theta >= 0 */
     double dar_clip;         /* C >= 0 (the paper's C_t, a constant per group) */
@@ -275,11 +290,11 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n,
  * through memory in between.  Results equal the visibility call followed
  * by adamw_gs_step with that mask, bit for bit.  cfg->schedule and
  * cfg->visible_hint are ignored.  means is normally the mean group's param
- * array (any [n][3] FP32 array works); visible_out [n] uint8 receives V, or
+ * array with its row stride (any [n][3] FP32 rows work); visible_out [n] uint8 receives V, or
  * is NULL.  Other arguments as for adamw_gs_step.
  */
 gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n,
-                             const float* means, const float* radius, const gs_camera* cams,
+                             const float* means, int64_t means_stride, const float* radius, const gs_camera* cams,
                              int32_t n_cams, uint8_t* visible_out, int32_t* step_count,
                              const gs_step_config* cfg, hipStream_t stream);
 
@@ -356,12 +371,13 @@ size_t gs_relocate_workspace_size(int64_t n);
  * Selects the k primitives with the smallest key (e.g. the opacity logit),
  * ties broken by the lower index, and zeroes their m and v in every group;
  * with reset_t also their step count.  key [n] FP32 device (finite values),
- * 0 <= k <= n.  selected [k] int32 out (ascending indices) or NULL.
+ * entries key_stride elements apart (0 = 1; e.g. the opacity column of a
+ * packed attribute array), 0 <= k <= n.  selected [k] int32 out (ascending indices) or NULL.
  * workspace: device memory of gs_relocate_workspace_size(n) bytes, 256-byte
  * aligned; contents on entry are ignored.  key must not overlap any group's
  * m or v, step_count or selected: rows are zeroed while keys are still read.
  */
-gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_group* groups,
+gs_status gs_relocate_reset(const float* key, int64_t key_stride, int64_t n, int64_t k, const gs_group* groups,
                             int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
                             int32_t reset_t, int32_t* selected, void* workspace,
                             size_t workspace_bytes, hipStream_t stream);
@@ -382,7 +398,8 @@ gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_gro
  * results; calls issued one after another on one stream do not.
  */
 #define GS_RELOCATE_NOALLOC_MAX_N ((int64_t)1 << 27)
-gs_status gs_relocate_reset_noalloc(const float* key, int64_t n, int64_t k, const gs_group* groups,
+gs_status gs_relocate_reset_noalloc(const float* key, int64_t key_stride, int64_t n, int64_t k,
+                                    const gs_group* groups,
                                     int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
                                     int32_t reset_t, int32_t* selected, hipStream_t stream);
 
@@ -422,10 +439,10 @@ size_t gs_spatial_order_workspace_size(int64_t n);
  * perm [n] int32 out: primitive indices sorted by the 30-bit Morton code of
  * their mean (10 bits per axis over the bounding box of the means; NaN
  * coordinates take part as the box minimum), ties in index order.
- * means [n][3] FP32.  workspace: gs_spatial_order_workspace_size(n) bytes,
- * 256-byte aligned.
+ * means [n][3] FP32, rows means_stride elements apart (0 = 3).  workspace:
+ * gs_spatial_order_workspace_size(n) bytes, 256-byte aligned.
  */
-gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* workspace,
+gs_status gs_spatial_order(const float* means, int64_t means_stride, int64_t n, int32_t* perm, void* workspace,
                            size_t workspace_bytes, hipStream_t stream);
 
 /*

@@ -59,7 +59,7 @@ class gs_camera(ctypes.Structure):
 class gs_group(ctypes.Structure):
     _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p),
                 ("exp_avg_sq", ctypes.c_void_p), ("dim", ctypes.c_int32), ("dar_kind", ctypes.c_int32),
-                ("reg_mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("reg_mode", ctypes.c_int32), ("row_stride", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("dar_lambda", ctypes.c_double), ("dar_clip", ctypes.c_double)]
 
 
@@ -90,12 +90,13 @@ _lib.gs_version.restype = _i32
 _lib.gs_reg_norm.restype = ctypes.c_double
 _lib.gs_reg_norm.argtypes = [ctypes.c_double]
 _lib.gs_visibility.restype = _i32
-_lib.gs_visibility.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
+_lib.gs_visibility.argtypes = [_vp, _i64, _vp, _i64, ctypes.POINTER(gs_camera), _vp, _vp, _vp, _vp]
 _lib.adamw_gs_step_view.restype = _i32
-_lib.adamw_gs_step_view.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _vp, ctypes.POINTER(gs_camera), _i32,
-                                    _vp, _vp, ctypes.POINTER(gs_step_config), _vp]
+_lib.adamw_gs_step_view.argtypes = [ctypes.POINTER(gs_group), _i32, _i64, _vp, _i64, _vp, ctypes.POINTER(gs_camera),
+                                    _i32, _vp, _vp, ctypes.POINTER(gs_step_config), _vp]
 _lib.gs_visibility_multi.restype = _i32
-_lib.gs_visibility_multi.argtypes = [_vp, _vp, _i64, ctypes.POINTER(gs_camera), _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.gs_visibility_multi.argtypes = [_vp, _i64, _vp, _i64, ctypes.POINTER(gs_camera), _i32, _vp, _vp, _vp, _vp,
+                                     _vp]
 _lib.gs_compact.restype = _i32
 _lib.gs_compact.argtypes = [_vp, _i64, _vp, _vp, _vp]
 _lib.adamw_gs_step.restype = _i32
@@ -114,11 +115,11 @@ _lib.gs_batch_destroy.argtypes = [_vp]
 _lib.gs_relocate_workspace_size.restype = _sz
 _lib.gs_relocate_workspace_size.argtypes = [_i64]
 _lib.gs_relocate_reset.restype = _i32
-_lib.gs_relocate_reset.argtypes = [_vp, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp, _vp,
-                                   _sz, _vp]
+_lib.gs_relocate_reset.argtypes = [_vp, _i64, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp,
+                                   _vp, _sz, _vp]
 _lib.gs_relocate_reset_noalloc.restype = _i32
-_lib.gs_relocate_reset_noalloc.argtypes = [_vp, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32, _vp,
-                                           _vp]
+_lib.gs_relocate_reset_noalloc.argtypes = [_vp, _i64, _i64, _i64, ctypes.POINTER(gs_group), _i32, _i32, _vp, _i32,
+                                           _vp, _vp]
 _lib.gs_tune.restype = _i32
 _lib.gs_tune.argtypes = [_i64, ctypes.POINTER(_i32), _i32, ctypes.c_float, _i32, ctypes.POINTER(_i32),
                          ctypes.POINTER(_i32)]
@@ -127,7 +128,7 @@ _lib.gs_tune_clear.argtypes = []
 _lib.gs_spatial_order_workspace_size.restype = _sz
 _lib.gs_spatial_order_workspace_size.argtypes = [_i64]
 _lib.gs_spatial_order.restype = _i32
-_lib.gs_spatial_order.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
+_lib.gs_spatial_order.argtypes = [_vp, _i64, _i64, _vp, _vp, _sz, _vp]
 _lib.gs_gather_rows.restype = _i32
 _lib.gs_gather_rows.argtypes = [_vp, _vp, _vp, _i64, _i64, _vp]
 _lib.gs_prune_workspace_size.restype = _sz
@@ -173,6 +174,26 @@ def last_error() -> str:
     return _lib.gs_last_error().decode()
 
 
+def _row_stride(t, dim: int) -> int:
+    """Elements from one row of t to the next, 0 when the rows are contiguous
+    (dim elements apart).  t is [n][dim] (or [n] for dim 1), possibly a
+    column slice of a wider packed tensor; objects without strides (plain
+    addresses) count as contiguous."""
+    if t is None or not hasattr(t, "stride") or isinstance(t, int):
+        return 0
+    if t.shape[0] <= 1 or any(d == 0 for d in t.shape):
+        return 0                        # no second row: the stride is never used
+    if len(t.shape) == 2:
+        if t.shape[1] > 1 and t.stride(1) != 1:
+            raise ValueError("attribute rows must have unit element stride")
+        s = int(t.stride(0))
+    elif len(t.shape) == 1:
+        s = int(t.stride(0))
+    else:
+        return 0
+    return 0 if s == dim else s
+
+
 def version() -> int:
     return int(_lib.gs_version())
 
@@ -212,8 +233,8 @@ class Camera:
 def gs_visibility(means, cam: Camera, mask=None, vis_idx=None, vis_count=None, radius=None, stream=None) -> None:
     n = int(means.shape[0])
     c = cam.to_c()
-    _check(_lib.gs_visibility(_ptr(means), _ptr(radius), n, ctypes.byref(c), _ptr(mask), _ptr(vis_idx),
-                              _ptr(vis_count), _stream(stream)))
+    _check(_lib.gs_visibility(_ptr(means), _row_stride(means, 3), _ptr(radius), n, ctypes.byref(c), _ptr(mask),
+                              _ptr(vis_idx), _ptr(vis_count), _stream(stream)))
 
 
 def gs_visibility_multi(means, cams: Sequence[Camera], mask=None, view_bits=None, vis_idx=None, vis_count=None,
@@ -221,8 +242,8 @@ def gs_visibility_multi(means, cams: Sequence[Camera], mask=None, view_bits=None
     """Up to 32 views at once: per-view bits (uint32 as int32 tensor), union mask, union indices."""
     n = int(means.shape[0])
     arr = (gs_camera * max(len(cams), 1))(*[c.to_c() for c in cams])
-    _check(_lib.gs_visibility_multi(_ptr(means), _ptr(radius), n, arr, len(cams), _ptr(mask), _ptr(view_bits),
-                                    _ptr(vis_idx), _ptr(vis_count), _stream(stream)))
+    _check(_lib.gs_visibility_multi(_ptr(means), _row_stride(means, 3), _ptr(radius), n, arr, len(cams), _ptr(mask),
+                                    _ptr(view_bits), _ptr(vis_idx), _ptr(vis_count), _stream(stream)))
 
 
 def gs_compact(mask, vis_idx, vis_count, stream=None) -> None:
@@ -241,17 +262,29 @@ class Group:
     dar_lambda: float = 0.0
     dar_clip: float = 0.0
     reg_mode: int = GS_REG_ADAPTIVE
+    row_stride: Optional[int] = None   # None: from the tensors' strides
 
     @property
     def dim(self) -> int:
         return int(self.param.shape[1]) if len(self.param.shape) > 1 else 1
+
+    def stride(self) -> int:
+        """The group's row stride (gs_group.row_stride): row_stride if set,
+        else read from the tensors, which must then agree."""
+        if self.row_stride is not None:
+            return int(self.row_stride)
+        found = {_row_stride(t, self.dim) for t in (self.param, self.grad, self.exp_avg, self.exp_avg_sq)
+                 if t is not None and hasattr(t, "stride")}
+        if len(found) > 1:
+            raise ValueError(f"param, grad and moments of a group need one row stride, got {sorted(found)}")
+        return found.pop() if found else 0
 
     def to_c(self) -> gs_group:
         g = gs_group()
         g.param, g.grad, g.exp_avg, g.exp_avg_sq = (_ptr(self.param), _ptr(self.grad), _ptr(self.exp_avg),
                                                     _ptr(self.exp_avg_sq))
         g.dim = self.dim
-        g.dar_kind, g.reg_mode, g.reserved = int(self.dar_kind), int(self.reg_mode), 0
+        g.dar_kind, g.reg_mode, g.row_stride = int(self.dar_kind), int(self.reg_mode), self.stride()
         g.lr, g.dar_lambda, g.dar_clip = float(self.lr), float(self.dar_lambda), float(self.dar_clip)
         return g
 
@@ -327,8 +360,8 @@ def adamw_gs_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepCon
     arr = _groups_c(groups)
     c = cfg.to_c()
     cc = (gs_camera * max(len(cams), 1))(*[x.to_c() for x in cams])
-    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _ptr(radius), cc, len(cams),
-                                   _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream)))
+    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _row_stride(means, 3), _ptr(radius), cc,
+                                   len(cams), _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream)))
 
 
 # --------------------------------------------------------------------------
@@ -411,8 +444,8 @@ def gs_relocate_reset(key, k: int, groups: Sequence[Group], moment_dtype: int, s
     arr = _groups_c(groups)
     n = int(key.shape[0])
     ws_bytes = int(workspace.numel() * workspace.element_size())
-    _check(_lib.gs_relocate_reset(_ptr(key), n, int(k), arr, len(groups), int(moment_dtype), _ptr(step_count),
-                                  int(bool(reset_t)), _ptr(selected), _ptr(workspace), ws_bytes,
+    _check(_lib.gs_relocate_reset(_ptr(key), _row_stride(key, 1), n, int(k), arr, len(groups), int(moment_dtype),
+                                  _ptr(step_count), int(bool(reset_t)), _ptr(selected), _ptr(workspace), ws_bytes,
                                   _stream(stream)))
 
 
@@ -426,8 +459,9 @@ def gs_relocate_reset_noalloc(key, k: int, groups: Sequence[Group], moment_dtype
     allocation, n <= GS_RELOCATE_NOALLOC_MAX_N (see include/gsopt.h)."""
     arr = _groups_c(groups)
     n = int(key.shape[0])
-    _check(_lib.gs_relocate_reset_noalloc(_ptr(key), n, int(k), arr, len(groups), int(moment_dtype),
-                                          _ptr(step_count), int(bool(reset_t)), _ptr(selected), _stream(stream)))
+    _check(_lib.gs_relocate_reset_noalloc(_ptr(key), _row_stride(key, 1), n, int(k), arr, len(groups),
+                                          int(moment_dtype), _ptr(step_count), int(bool(reset_t)), _ptr(selected),
+                                          _stream(stream)))
 
 
 def gs_tune(n: int, dims: Sequence[int], visible_fraction: float, moment_dtype: int = GS_MOMENT_F32):
@@ -451,8 +485,8 @@ def gs_spatial_order_workspace_size(n: int) -> int:
 def gs_spatial_order(means, perm, workspace, stream=None) -> None:
     """perm <- primitive indices in Morton order of their means."""
     ws_bytes = int(workspace.numel() * workspace.element_size())
-    _check(_lib.gs_spatial_order(_ptr(means), int(means.shape[0]), _ptr(perm), _ptr(workspace), ws_bytes,
-                                 _stream(stream)))
+    _check(_lib.gs_spatial_order(_ptr(means), _row_stride(means, 3), int(means.shape[0]), _ptr(perm),
+                                 _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def gs_gather_rows(src, dst, perm, stream=None) -> None:

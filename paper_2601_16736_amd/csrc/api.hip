@@ -1,7 +1,9 @@
 // Host side of the C ABI: argument validation, FP32 constants prepared in
 // double, schedule choice and launches.  Declarations and contracts: gsopt.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -82,6 +84,63 @@ gs_status set_error(gs_status s, const char* msg)
 
 void clear_error() { t_err.clear(); }
 
+// Row stride of a means array: 0 means 3 (contiguous [n][3]); otherwise at
+// least 3, and the rows must stay inside 2^40 elements.
+static bool means_rows(int64_t stride, int64_t n, int64_t* out)
+{
+    const int64_t ms = stride == 0 ? 3 : stride;
+    if (ms < 3 || ms > 65536 || ms * n >= ((int64_t)1 << 40)) return false;
+    *out = ms;
+    return true;
+}
+
+void plan_packed_rows(KScene& s, size_t msz)
+{
+    s.pk_stride = 0;
+    s.pk_param = nullptr;
+    s.pk_grad = nullptr;
+    s.pk_m = nullptr;
+    s.pk_v = nullptr;
+    for (int g = 0; g < GS_MAX_GROUPS; ++g) s.pk_col[g] = 0;
+    if (s.n_groups < 1) return;
+    const int32_t S = s.g[0].stride;
+    if (S < 4 || S > 256 || (S & (S - 1)) != 0) return;
+    uintptr_t bp = UINTPTR_MAX, bg = UINTPTR_MAX, bm = UINTPTR_MAX, bv = UINTPTR_MAX;
+    for (int g = 0; g < s.n_groups; ++g) {
+        const KGroup& G = s.g[g];
+        if (G.stride != S || G.param == nullptr) return;
+        bp = std::min(bp, (uintptr_t)G.param);
+        bg = std::min(bg, (uintptr_t)G.grad);
+        bm = std::min(bm, (uintptr_t)G.m);
+        bv = std::min(bv, (uintptr_t)G.v);
+    }
+    if (bp % 16 || bg % 16 || bm % (4 * msz) || bv % (4 * msz)) return;
+    uint64_t used = 0;                  // columns 0..63 taken so far
+    uint64_t used_hi[3] = {0, 0, 0};    // columns 64..255
+    for (int g = 0; g < s.n_groups; ++g) {
+        const KGroup& G = s.g[g];
+        const uintptr_t dp = (uintptr_t)G.param - bp;
+        if (dp % 4) return;
+        const int64_t col = (int64_t)(dp / 4);
+        if (col + G.dim > S) return;
+        if ((uintptr_t)G.grad - bg != dp || (uintptr_t)G.m - bm != (uintptr_t)col * msz ||
+            (uintptr_t)G.v - bv != (uintptr_t)col * msz)
+            return;
+        for (int64_t c = col; c < col + G.dim; ++c) {
+            uint64_t& word = c < 64 ? used : used_hi[c / 64 - 1];
+            const uint64_t bit = (uint64_t)1 << (c % 64);
+            if (word & bit) return;                  // two groups share a column
+            word |= bit;
+        }
+        s.pk_col[g] = (int32_t)col;
+    }
+    s.pk_stride = S;
+    s.pk_param = reinterpret_cast<float*>(bp);
+    s.pk_grad = reinterpret_cast<const float*>(bg);
+    s.pk_m = reinterpret_cast<void*>(bm);
+    s.pk_v = reinterpret_cast<void*>(bv);
+}
+
 // Validates one scene's groups and fills the kernel view.  Prefix names the
 // scene in messages.
 gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int32_t moment_dtype,
@@ -95,8 +154,11 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
     for (int g = 0; g < n_groups; ++g) {
         const gs_group& G = groups[g];
         if (G.dim < 1 || G.dim > 4096) return fail(GS_EINVAL, "%sgroup %d: dim = %d, must be in [1, 4096]", prefix, g, G.dim);
-        if ((int64_t)G.dim * n >= ((int64_t)1 << 40))
-            return fail(GS_EINVAL, "%sgroup %d: n * dim too large", prefix, g);
+        if (G.row_stride != 0 && (G.row_stride < G.dim || G.row_stride > 65536))
+            return fail(GS_EINVAL, "%sgroup %d: row_stride = %d, must be 0 or in [dim, 65536]", prefix, g, G.row_stride);
+        const int32_t stride = G.row_stride != 0 ? G.row_stride : G.dim;
+        if ((int64_t)stride * n >= ((int64_t)1 << 40))
+            return fail(GS_EINVAL, "%sgroup %d: n * row stride too large", prefix, g);
         if (n > 0 && (G.param == nullptr || G.grad == nullptr || G.exp_avg == nullptr || G.exp_avg_sq == nullptr))
             return fail(GS_EINVAL, "%sgroup %d: param, grad, exp_avg and exp_avg_sq must be non-NULL", prefix, g);
         if (!aligned(G.param, 4) || !aligned(G.grad, 4) || !aligned(G.exp_avg, msz) || !aligned(G.exp_avg_sq, msz))
@@ -105,7 +167,6 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
             return fail(GS_EINVAL, "%sgroup %d: unknown dar_kind %d", prefix, g, G.dar_kind);
         if (G.reg_mode < GS_REG_ADAPTIVE || G.reg_mode > GS_REG_CONSTANT_CLIPPED)
             return fail(GS_EINVAL, "%sgroup %d: unknown reg_mode %d", prefix, g, G.reg_mode);
-        if (G.reserved != 0) return fail(GS_EINVAL, "%sgroup %d: reserved must be 0", prefix, g);
         if (!finite_d(G.lr)) return fail(GS_EINVAL, "%sgroup %d: lr must be finite", prefix, g);
         if (!(G.dar_lambda >= 0.0) || !finite_d(G.dar_lambda))
             return fail(GS_EINVAL, "%sgroup %d: dar_lambda must be finite and >= 0", prefix, g);
@@ -117,12 +178,13 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
         K.m = G.exp_avg;
         K.v = G.exp_avg_sq;
         K.dim = G.dim;
+        // a row's accesses are as wide as its length, stride and pointers allow
         int vec = 1;
-        if (G.dim % 4 == 0 && aligned(G.param, 16) && aligned(G.grad, 16) && aligned(G.exp_avg, 4 * msz) &&
-            aligned(G.exp_avg_sq, 4 * msz))
+        if (G.dim % 4 == 0 && stride % 4 == 0 && aligned(G.param, 16) && aligned(G.grad, 16) &&
+            aligned(G.exp_avg, 4 * msz) && aligned(G.exp_avg_sq, 4 * msz))
             vec = 4;
-        else if (G.dim % 2 == 0 && aligned(G.param, 8) && aligned(G.grad, 8) && aligned(G.exp_avg, 2 * msz) &&
-                 aligned(G.exp_avg_sq, 2 * msz))
+        else if (G.dim % 2 == 0 && stride % 2 == 0 && aligned(G.param, 8) && aligned(G.grad, 8) &&
+                 aligned(G.exp_avg, 2 * msz) && aligned(G.exp_avg_sq, 2 * msz))
             vec = 2;
         K.vec = vec;
         K.cpr = G.dim / vec;
@@ -130,7 +192,7 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
         K.dar_kind = G.dar_kind;
         K.reg_mode = G.reg_mode;
         K.dar_clip = std::isinf(G.dar_clip) ? INFINITY : (float)G.dar_clip;
-        K.pad = 0;
+        K.stride = stride;
         K.dar_lambda = G.dar_lambda;
     }
     (void)cfg;
@@ -138,6 +200,7 @@ gs_status build_groups(const gs_group* groups, int32_t n_groups, int64_t n, int3
     out->n_groups = n_groups;
     out->bf16 = bf16 ? 1 : 0;
     out->n = n;
+    plan_packed_rows(*out, msz);
     return GS_OK;
 }
 
@@ -316,11 +379,13 @@ static gs_status to_kcamera(const gs_camera* cam, KCamera* k, const char* prefix
     return GS_OK;
 }
 
-gs_status gs_visibility(const float* means, const float* radius, int64_t n, const gs_camera* cam, uint8_t* mask,
-                        int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
+gs_status gs_visibility(const float* means, int64_t means_stride, const float* radius, int64_t n,
+                        const gs_camera* cam, uint8_t* mask, int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
 {
     clear_error();
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    int64_t ms = 0;
+    if (!means_rows(means_stride, n, &ms)) return fail(GS_EINVAL, "means_stride = %lld: must be 0 or >= 3 (and n * stride < 2^40)", (long long)means_stride);
     if (cam == nullptr) return fail(GS_EINVAL, "cam is NULL");
     if (mask == nullptr && vis_idx == nullptr) return fail(GS_EINVAL, "mask and vis_idx are both NULL");
     if (vis_idx != nullptr && vis_count == nullptr) return fail(GS_EINVAL, "vis_idx needs vis_count");
@@ -330,16 +395,18 @@ gs_status gs_visibility(const float* means, const float* radius, int64_t n, cons
     KCamera k;
     const gs_status st = to_kcamera(cam, &k, "");
     if (st != GS_OK) return st;
-    const hipError_t e = launch_visibility(means, radius, n, k, mask, vis_idx, vis_count, stream);
+    const hipError_t e = launch_visibility(means, ms, radius, n, k, mask, vis_idx, vis_count, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_visibility launch");
 }
 
-gs_status gs_visibility_multi(const float* means, const float* radius, int64_t n, const gs_camera* cams,
-                              int32_t n_cams, uint8_t* mask, uint32_t* view_bits, int32_t* vis_idx,
-                              int32_t* vis_count, hipStream_t stream)
+gs_status gs_visibility_multi(const float* means, int64_t means_stride, const float* radius, int64_t n,
+                              const gs_camera* cams, int32_t n_cams, uint8_t* mask, uint32_t* view_bits,
+                              int32_t* vis_idx, int32_t* vis_count, hipStream_t stream)
 {
     clear_error();
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    int64_t ms = 0;
+    if (!means_rows(means_stride, n, &ms)) return fail(GS_EINVAL, "means_stride = %lld: must be 0 or >= 3 (and n * stride < 2^40)", (long long)means_stride);
     if (cams == nullptr) return fail(GS_EINVAL, "cams is NULL");
     if (n_cams < 1 || n_cams > kMaxViews) return fail(GS_EINVAL, "n_cams = %d, must be in [1, %d]", n_cams, kMaxViews);
     if (mask == nullptr && view_bits == nullptr && vis_idx == nullptr)
@@ -358,7 +425,7 @@ gs_status gs_visibility_multi(const float* means, const float* radius, int64_t n
         if (st != GS_OK) return st;
     }
     k.n = n_cams;
-    const hipError_t e = launch_visibility_multi(means, radius, n, k, mask, view_bits, vis_idx, vis_count, stream);
+    const hipError_t e = launch_visibility_multi(means, ms, radius, n, k, mask, view_bits, vis_idx, vis_count, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_visibility_multi launch");
 }
 
@@ -407,18 +474,25 @@ gs_status adamw_gs_step(const gs_group* groups, int32_t n_groups, int64_t n, con
     s.idx = vis_idx;
     s.count = vis_count;
     s.t = step_count;
-    trace_step("adamw_gs_step", n, n_groups,
-               sched == kSchedCompacted ? "compacted" : sched == kSchedMasked ? "masked" : "dense", unit, cfg, "");
+    if (trace_on()) {
+        char detail[32] = "";
+        if (s.pk_stride > 0) snprintf(detail, sizeof detail, "rows=packed%d", s.pk_stride);
+        trace_step("adamw_gs_step", n, n_groups,
+                   sched == kSchedCompacted ? "compacted" : sched == kSchedMasked ? "masked" : "dense", unit, cfg,
+                   detail);
+    }
     const hipError_t e = launch_step(s, h, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step launch");
 }
 
 gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n, const float* means,
-                             const float* radius, const gs_camera* cams, int32_t n_cams, uint8_t* visible_out,
-                             int32_t* step_count, const gs_step_config* cfg, hipStream_t stream)
+                             int64_t means_stride, const float* radius, const gs_camera* cams, int32_t n_cams,
+                             uint8_t* visible_out, int32_t* step_count, const gs_step_config* cfg, hipStream_t stream)
 {
     clear_error();
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(GS_EINVAL, "n = %lld, must be in [0, 2^31)", (long long)n);
+    int64_t ms = 0;
+    if (!means_rows(means_stride, n, &ms)) return fail(GS_EINVAL, "means_stride = %lld: must be 0 or >= 3 (and n * stride < 2^40)", (long long)means_stride);
     if (cams == nullptr) return fail(GS_EINVAL, "cams is NULL");
     if (n_cams < 1 || n_cams > kMaxViews) return fail(GS_EINVAL, "n_cams = %d, must be in [1, %d]", n_cams, kMaxViews);
     if (n > 0 && (step_count == nullptr || means == nullptr)) return fail(GS_EINVAL, "step_count or means is NULL");
@@ -455,11 +529,12 @@ gs_status adamw_gs_step_view(const gs_group* groups, int32_t n_groups, int64_t n
     s.unit = fit_unit(n, unit, 256);
     s.t = step_count;
     if (trace_on()) {
-        char detail[32];
-        snprintf(detail, sizeof detail, "views=%d", n_cams);
+        char detail[48];
+        if (s.pk_stride > 0) snprintf(detail, sizeof detail, "views=%d rows=packed%d", n_cams, s.pk_stride);
+        else snprintf(detail, sizeof detail, "views=%d", n_cams);
         trace_step("adamw_gs_step_view", n, n_groups, "view", s.unit, cfg, detail);
     }
-    const hipError_t e = launch_step_view(s, h, k, means, radius, visible_out, stream);
+    const hipError_t e = launch_step_view(s, h, k, means, ms, radius, visible_out, stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "adamw_gs_step_view launch");
 }
 

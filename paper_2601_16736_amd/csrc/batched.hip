@@ -50,7 +50,7 @@ struct KBatch {
     int32_t inv_first[kMaxScenes + 1];        // first invisible unit of each scene, after all step units
 };
 
-template <bool BF16, bool NOISE>
+template <bool BF16, bool NOISE, bool PACKED>
 __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int64_t local, int* s_row, float* s_rb1,
                                           float* s_rsb2, float* s_noise, int lane)
 {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
         wave_sync();
         stage_step_rows(nrows, s_row, s_rb1, s_rsb2, S.t, H, d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
-        step_all_groups<BF16, NOISE, kBatchUnroll>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane, s_noise);
+        step_all_groups<BF16, NOISE, kBatchUnroll, PACKED>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane, s_noise);
     }
     wave_sync();   // the next unit reuses this wave's LDS rows
 }
@@ -110,8 +110,8 @@ __device__ __forceinline__ int scene_of(const int32_t* first, int n_scenes, int6
     return s;
 }
 
-template <bool BF16, bool NOISE>
-__global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
+template <bool BF16, bool NOISE, bool PACKED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void batched_kernel(KBatch B, KHyper H)
 {
     __shared__ int s_row[kWavesPerBlock][kBatchCap];
     __shared__ float s_rb1[kWavesPerBlock][kBatchCap];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(KBatch B, KHyper H)
     for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave; u < total; u += stride) {
         if (u < steps) {
             const int s = scene_of(B.step_first, B.n_scenes, u);
-            step_unit<BF16, NOISE>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave],
+            step_unit<BF16, NOISE, PACKED>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave],
                                    s_noise[wave], lane);
         } else {
             const int64_t v = u - steps;
@@ -145,6 +145,7 @@ struct gs_batch {
     int32_t n_scenes = 0;
     int32_t moment_dtype = 0;
     bool any_adaptive = false;
+    bool any_packed = false;                    // some scene has packed rows
     std::vector<KScene> h_scenes;
     std::vector<int32_t> sched;
     KScene* d_scenes = nullptr;
@@ -159,13 +160,22 @@ struct gs_batch {
 
 namespace {
 
-void* kernel_for(int moment_dtype, int noise)
+// packed: some scene of the plan has packed rows (those kernels also carry
+// the per-group passes, for the plan's other scenes)
+void* kernel_for(int moment_dtype, int noise, bool packed)
 {
+    if (packed) {
+        if (moment_dtype == GS_MOMENT_BF16)
+            return noise ? reinterpret_cast<void*>(&batched_kernel<true, true, true>)
+                         : reinterpret_cast<void*>(&batched_kernel<true, false, true>);
+        return noise ? reinterpret_cast<void*>(&batched_kernel<false, true, true>)
+                     : reinterpret_cast<void*>(&batched_kernel<false, false, true>);
+    }
     if (moment_dtype == GS_MOMENT_BF16)
-        return noise ? reinterpret_cast<void*>(&batched_kernel<true, true>)
-                     : reinterpret_cast<void*>(&batched_kernel<true, false>);
-    return noise ? reinterpret_cast<void*>(&batched_kernel<false, true>)
-                 : reinterpret_cast<void*>(&batched_kernel<false, false>);
+        return noise ? reinterpret_cast<void*>(&batched_kernel<true, true, false>)
+                     : reinterpret_cast<void*>(&batched_kernel<true, false, false>);
+    return noise ? reinterpret_cast<void*>(&batched_kernel<false, true, false>)
+                 : reinterpret_cast<void*>(&batched_kernel<false, false, false>);
 }
 
 void free_batch(gs_batch* b)
@@ -220,6 +230,7 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
             free_batch(b);
             return st;
         }
+        if (K.pk_stride > 0) b->any_packed = true;
         int32_t dims[GS_MAX_GROUPS];
         for (int g = 0; g < sc.n_groups; ++g) {
             dims[g] = sc.groups[g].dim;
@@ -308,8 +319,10 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     if (trace_on()) {
         int64_t n_all = 0;
         for (const KScene& K : b->h_scenes) n_all += K.n;
-        char detail[64];
-        snprintf(detail, sizeof detail, "scenes=%d waves=%lld", b->n_scenes, (long long)units);
+        int packed = 0;
+        for (const KScene& K : b->h_scenes) packed += K.pk_stride > 0;
+        char detail[96];
+        snprintf(detail, sizeof detail, "scenes=%d waves=%lld packed=%d", b->n_scenes, (long long)units, packed);
         trace_step("adamw_gs_step_batched", n_all, b->h_scenes.empty() ? 0 : b->h_scenes[0].n_groups,
                    b->persistent_blocks > 0 ? "plan-resident" : "plan", 0, cfg, detail);
     }
@@ -320,7 +333,7 @@ extern "C" gs_status adamw_gs_step_batched(gs_batch* b, const gs_step_config* cf
     void* args[] = {&b->kb, &b->kh};
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
-    p.func = kernel_for(b->moment_dtype, v);
+    p.func = kernel_for(b->moment_dtype, v, b->any_packed);
     const int64_t blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
     // the waves stride over the units, so a grid capped at one dispatch's
     // limit still covers them all
@@ -360,7 +373,7 @@ extern "C" gs_status gs_batch_set_resident(gs_batch* b, int32_t resident)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(kernel_for(b->moment_dtype, 0)), kBlock, 0) != hipSuccess)
+            &per_cu, reinterpret_cast<const void*>(kernel_for(b->moment_dtype, 0, b->any_packed)), kBlock, 0) != hipSuccess)
         return set_error(GS_EHIP, "gs_batch_set_resident: device query failed");
     b->persistent_blocks = (int64_t)cus * std::max(1, per_cu);
     return GS_OK;

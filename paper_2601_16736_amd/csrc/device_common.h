@@ -156,24 +156,26 @@ template <bool BF16, int V> __device__ __forceinline__ void load_moment(const vo
 // upper 16, v the lower 16), so one draw serves two consecutive elements.
 __device__ __forceinline__ uint32_t sr_word(uint64_t d, int64_t e) { return (e & 1) ? (uint32_t)d : (uint32_t)(d >> 32); }
 
-// Stores m and v of V consecutive elements starting at element e (for V > 1,
-// e is a multiple of V: vector access needs dim % V == 0).  BF16 with
+// Stores m and v of V consecutive elements at array offset e; el is the
+// first one's element index row * dim + column in its group, which keys its
+// rounding bits (for V > 1 both are multiples of V: vector access needs
+// dim % V == 0 and a row stride that is a multiple of V).  BF16 with
 // stochastic rounding takes the bits of sr_word.
 template <bool BF16, int V>
-__device__ __forceinline__ void store_moments(void* mb, void* vb, int64_t e, const float* m, const float* v,
-                                              bool sr, uint64_t s2)
+__device__ __forceinline__ void store_moments(void* mb, void* vb, int64_t e, int64_t el, const float* m,
+                                              const float* v, bool sr, uint64_t s2)
 {
     if constexpr (BF16) {
         uint32_t hm[V], hv[V];
         if (sr) {
             if constexpr (V == 1) {
-                const uint32_t w = sr_word(d_splitmix(s2, (uint64_t)(e >> 1) + 1), e);
+                const uint32_t w = sr_word(d_splitmix(s2, (uint64_t)(el >> 1) + 1), el);
                 hm[0] = f32_to_bf16_sr(m[0], w >> 16);
                 hv[0] = f32_to_bf16_sr(v[0], w & 0xFFFFu);
             } else {
 #pragma unroll
                 for (int q = 0; q < V; q += 2) {
-                    const uint64_t d = d_splitmix(s2, (uint64_t)((e + q) >> 1) + 1);
+                    const uint64_t d = d_splitmix(s2, (uint64_t)((el + q) >> 1) + 1);
                     const uint32_t hi = (uint32_t)(d >> 32), lo = (uint32_t)d;
                     hm[q] = f32_to_bf16_sr(m[q], hi >> 16);
                     hv[q] = f32_to_bf16_sr(v[q], hi & 0xFFFFu);
@@ -220,6 +222,7 @@ struct NoiseArgs {
     const float* q;      // quaternion group's attributes
     const float* kappa;  // log-scale group's attributes
     const float* tau;    // opacity-logit group's attributes
+    int64_t sq, sk, st;  // their row strides in elements
     uint64_t s2;         // stream (seed, tag 48, iteration)
     float scale;         // eta_{R_o} * eta_mu
 };
@@ -246,23 +249,44 @@ __device__ __forceinline__ void noise_row(const NoiseArgs& nz, int64_t i, float 
     // rotation of the normalised quaternion (w, x, y, z)
     const float* qp = nz.q;
     const float* kp = nz.kappa;
-    float w = qp[4 * i], x = qp[4 * i + 1], y = qp[4 * i + 2], z = qp[4 * i + 3];
+    float w = qp[nz.sq * i], x = qp[nz.sq * i + 1], y = qp[nz.sq * i + 2], z = qp[nz.sq * i + 3];
     const float inv = 1.0f / __fsqrt_rn(w * w + x * x + y * y + z * z);
     w *= inv; x *= inv; y *= inv; z *= inv;
     const float R00 = 1.0f - 2.0f * (y * y + z * z), R01 = 2.0f * (x * y - w * z), R02 = 2.0f * (x * z + w * y);
     const float R10 = 2.0f * (x * y + w * z), R11 = 1.0f - 2.0f * (x * x + z * z), R12 = 2.0f * (y * z - w * x);
     const float R20 = 2.0f * (x * z - w * y), R21 = 2.0f * (y * z + w * x), R22 = 1.0f - 2.0f * (x * x + y * y);
     // Sigma gamma = R diag(exp(2 kappa)) R^T gamma
-    const float e0 = (R00 * g0 + R10 * g1 + R20 * g2) * expf(2.0f * kp[3 * i]);
-    const float e1 = (R01 * g0 + R11 * g1 + R21 * g2) * expf(2.0f * kp[3 * i + 1]);
-    const float e2 = (R02 * g0 + R12 * g1 + R22 * g2) * expf(2.0f * kp[3 * i + 2]);
-    const float o = 1.0f / (1.0f + expf(-nz.tau[i]));
+    const float e0 = (R00 * g0 + R10 * g1 + R20 * g2) * expf(2.0f * kp[nz.sk * i]);
+    const float e1 = (R01 * g0 + R11 * g1 + R21 * g2) * expf(2.0f * kp[nz.sk * i + 1]);
+    const float e2 = (R02 * g0 + R12 * g1 + R22 * g2) * expf(2.0f * kp[nz.sk * i + 2]);
+    const float o = 1.0f / (1.0f + expf(-nz.tau[nz.st * i]));
     const float gate = 1.0f / (1.0f + expf(k * (o - t0)));            // sigma(-k (o - t))
     out[0] = nz.scale * gate * (R00 * e0 + R01 * e1 + R02 * e2);
     out[1] = nz.scale * gate * (R10 * e0 + R11 * e1 + R12 * e2);
     out[2] = nz.scale * gate * (R20 * e0 + R21 * e1 + R22 * e2);
 }
 
+
+// The update of one visible element (sparse-beta, decoupled-moment, Adam
+// and DAR update equations): the moments from the photometric gradient g
+// (c1, c2: beta, or beta*alpha for a row in this iteration's Re-State
+// sample), the Adam direction from the bias corrections rb1 = 1/(1-beta1^t)
+// and rsb2 = 1/sqrt(1-beta2^t), the regulariser term at the pre-update
+// theta (dar: kind != GS_DAR_NONE), and theta.  Every schedule calls this
+// one function, so they all round alike.
+__device__ __forceinline__ void update_element(float& th, float g, float& m, float& v, float c1, float c2, float rb1,
+                                               float rsb2, const KHyper& H, bool dar, int kind, int mode, float scale,
+                                               float clip, float lr)
+{
+    const float mm = c1 * m + H.omb1 * g;
+    const float vv = c2 * v + H.omb2 * (g * g);
+    const float d = __fsqrt_rn(vv) * rsb2 + H.eps;       // sqrt(v / b2) + eps
+    float uu = (mm * rb1) / d;                            // (m / b1) / d
+    if (dar) uu += reg_term(kind, mode, scale, clip, th, d);
+    th = th - lr * uu;
+    m = mm;
+    v = vv;
+}
 
 // One group's read-modify-write pass over the wave's staged rows.  Each
 // lane takes U (row, chunk) items per trip and issues all their loads before
@@ -276,6 +300,7 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
+    const int64_t stride = G.stride;
     const int items = nrows * cpr;
     int r = lane / cpr;
     int c = lane - r * cpr;
@@ -283,7 +308,7 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
     const int dc = kWave - dr * cpr;
     const bool dar = G.dar_kind != GS_DAR_NONE;
     for (int k0 = lane; k0 < items; k0 += U * kWave) {
-        int64_t e[U];
+        int64_t e[U], el[U];   // array offset, element index in the group
         float c1[U], c2[U], rb1[U], rsb2[U];
         bool ok[U];
         int nidx[U];      // NOISE: the item's slot in s_noise
@@ -298,7 +323,8 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
             c2[u] = raw < 0 ? H.c2_rsr : H.beta2;
             rb1[u] = ok[u] ? s_rb1[r] : 1.0f;
             rsb2[u] = ok[u] ? s_rsb2[r] : 1.0f;
-            e[u] = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
+            e[u] = (int64_t)(raw & 0x7FFFFFFF) * stride + c * V;
+            el[u] = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
             r += dr;
             c += dc;
             if (c >= cpr) { c -= cpr; ++r; }
@@ -318,18 +344,12 @@ __device__ __forceinline__ void step_group(const KGroup& G, const KHyper& H, int
             if (!ok[u]) continue;
 #pragma unroll
             for (int q = 0; q < V; ++q) {
-                const float mm = c1[u] * m[u][q] + H.omb1 * g[u][q];
-                const float vv = c2[u] * v[u][q] + H.omb2 * (g[u][q] * g[u][q]);
-                const float d = __fsqrt_rn(vv) * rsb2[u] + H.eps;       // sqrt(v / b2) + eps
-                float uu = (mm * rb1[u]) / d;                            // (m / b1) / d
-                if (dar) uu += reg_term(G.dar_kind, G.reg_mode, dar_scale, G.dar_clip, th[u][q], d);
-                th[u][q] = th[u][q] - G.lr * uu;
+                update_element(th[u][q], g[u][q], m[u][q], v[u][q], c1[u], c2[u], rb1[u], rsb2[u], H, dar,
+                               G.dar_kind, G.reg_mode, dar_scale, G.dar_clip, G.lr);
                 if constexpr (NOISE) th[u][q] -= s_noise[nidx[u]];     // the mean group: dim 3, V = 1
-                m[u][q] = mm;
-                v[u][q] = vv;
             }
             store_f<V>(G.param + e[u], th[u]);
-            store_moments<BF16, V>(G.m, G.v, e[u], m[u], v[u], H.sr != 0, sr_s2);
+            store_moments<BF16, V>(G.m, G.v, e[u], el[u], m[u], v[u], H.sr != 0, sr_s2);
         }
     }
 }
@@ -346,6 +366,7 @@ __device__ __forceinline__ void invisible_group(const KGroup& G, const KHyper& H
 {
     const int cpr = G.cpr;
     const int dim = G.dim;
+    const int64_t stride = G.stride;
     const int items = nrows * cpr;
     int r = lane / cpr;
     int c = lane - r * cpr;
@@ -357,7 +378,8 @@ __device__ __forceinline__ void invisible_group(const KGroup& G, const KHyper& H
         const float rsb2 = s_rsb2[r];
         const bool rsr = raw < 0;
         const bool aiu = rb1 > 0.0f;
-        const int64_t e = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
+        const int64_t e = (int64_t)(raw & 0x7FFFFFFF) * stride + c * V;
+        const int64_t el = (int64_t)(raw & 0x7FFFFFFF) * dim + c * V;
         float m[V], v[V], th[V];
         load_moment<BF16, V>(G.m, e, m);
         load_moment<BF16, V>(G.v, e, v);
@@ -368,7 +390,7 @@ __device__ __forceinline__ void invisible_group(const KGroup& G, const KHyper& H
                 m[q] = H.rsr_a1 * m[q];
                 v[q] = H.rsr_a2 * v[q];
             }
-            store_moments<BF16, V>(G.m, G.v, e, m, v, H.sr != 0, sr_s2);
+            store_moments<BF16, V>(G.m, G.v, e, el, m, v, H.sr != 0, sr_s2);
         }
         if (aiu) {
 #pragma unroll
@@ -500,10 +522,156 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
     }
 }
 
+// ---------------------------------------------------------------- packed rows
+// The packed pass (KScene::pk_stride > 0): every group is a column range of
+// the same [n][S] arrays, so the step takes each staged row in one pass of
+// 4-column chunks (16-byte attribute, 4-element moment accesses) instead of
+// one pass per group.  S / 4 divides the wave, so a lane meets the same
+// chunk in every row it visits: the group of each of its 4 columns and that
+// group's hyper-parameters are set up once per pass.  A column outside every
+// group is read and written back unchanged (the same bits), so that every
+// chunk is stored with one access per array and a row's lines are written
+// whole: the HBM has no byte masks, and a line written in part costs its
+// controller a read-modify-write.  Each element's update is step_group's;
+// a BF16 element's rounding bits come from its index row * dim + column in
+// its own group, exactly as in the per-group passes, so both schedules give
+// the same bits.
+template <bool BF16, int U, bool NOISE>
+__device__ __forceinline__ void step_packed(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
+                                            const int* s_row, const float* s_rb1, const float* s_rsb2, int lane,
+                                            const float* s_noise)
+{
+    const int cpr = S.pk_stride >> 2;          // chunks per row, a power of two up to 64
+    const int chunk = lane & (cpr - 1);
+    const int rstep = kWave / cpr;             // rows that one wave-wide trip covers
+    // the lane's 4 columns: group (-1: none), DAR, lr, rounding stream and
+    // place in the group (element index = row * dim + off)
+    int gid[4], kind[4], mode[4], dim[4], off[4];
+    float lr[4], scale[4], clip[4];
+    uint64_t s2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gid[q] = -1;
+        kind[q] = GS_DAR_NONE;
+        mode[q] = GS_REG_ADAPTIVE;
+        dim[q] = 1;
+        off[q] = 0;
+        lr[q] = 0.0f;
+        scale[q] = 0.0f;
+        clip[q] = 0.0f;
+        s2[q] = 0;
+    }
+    for (int gi = 0; gi < S.n_groups; ++gi) {
+        const KGroup& G = S.g[gi];
+        const int lo = S.pk_col[gi];
+        // lambda / N_I' rounded once from double, exactly as a host would form it
+        const float sc = (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
+                             ? (float)(G.dar_lambda / H.reg_norm)
+                             : (float)G.dar_lambda;
+        const uint64_t gs2 = BF16 ? d_stream(seed, kTagSrStep + (uint64_t)gi, H.iteration) : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int col = 4 * chunk + q;
+            if (col >= lo && col < lo + G.dim) {
+                gid[q] = gi;
+                kind[q] = G.dar_kind;
+                mode[q] = G.reg_mode;
+                dim[q] = G.dim;
+                off[q] = col - lo;
+                lr[q] = G.lr;
+                scale[q] = sc;
+                clip[q] = G.dar_clip;
+                s2[q] = gs2;
+            }
+        }
+    }
+    const bool sr = H.sr != 0;
+    const int64_t stride = S.pk_stride;
+    for (int r0 = lane / cpr; r0 < nrows; r0 += U * rstep) {
+        int rr[U];
+        bool ok[U];
+        int64_t row[U];
+        float th[U][4], g[U][4], m[U][4], v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rr[u] = r0 + u * rstep;
+            ok[u] = rr[u] < nrows;
+            row[u] = ok[u] ? (int64_t)(s_row[rr[u]] & 0x7FFFFFFF) : 0;
+            if (ok[u]) {
+                const int64_t e = row[u] * stride + 4 * chunk;
+                load_f<4>(S.pk_param + e, th[u]);
+                load_f<4>(S.pk_grad + e, g[u]);
+                load_moment<BF16, 4>(S.pk_m, e, m[u]);
+                load_moment<BF16, 4>(S.pk_v, e, v[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const int raw = s_row[rr[u]];
+            // a row in this iteration's Re-State sample decays by alpha before
+            // the moment update: beta*(alpha*m) folded into (beta*alpha)*m
+            const float c1 = raw < 0 ? H.c1_rsr : H.beta1;
+            const float c2 = raw < 0 ? H.c2_rsr : H.beta2;
+            const float rb1 = s_rb1[rr[u]];
+            const float rsb2 = s_rsb2[rr[u]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (gid[q] < 0) continue;
+                update_element(th[u][q], g[u][q], m[u][q], v[u][q], c1, c2, rb1, rsb2, H, kind[q] != GS_DAR_NONE,
+                               kind[q], mode[q], scale[q], clip[q], lr[q]);
+                if (NOISE && gid[q] == H.noise_g[0]) th[u][q] -= s_noise[3 * rr[u] + off[q]];
+            }
+            const int64_t e = row[u] * stride + 4 * chunk;
+            if constexpr (BF16) {
+                uint32_t hm[4], hv[4];
+                if (sr) {
+                    // one draw serves m and v of an element and of its pair
+                    // partner (sr_word): the chunk's columns reuse the draw
+                    // of the column before them when it is the same pair
+                    uint64_t d = 0;
+                    int64_t key_prev = -1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t el = row[u] * dim[q] + off[q];
+                        const int64_t key = el >> 1;
+                        if (gid[q] >= 0 && (q == 0 || gid[q] != gid[q - 1] || key != key_prev))
+                            d = d_splitmix(s2[q], (uint64_t)key + 1);
+                        key_prev = key;
+                        const uint32_t w = sr_word(d, el);
+                        hm[q] = f32_to_bf16_sr(m[u][q], w >> 16);
+                        hv[q] = f32_to_bf16_sr(v[u][q], w & 0xFFFFu);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        hm[q] = f32_to_bf16_rne(m[u][q]);
+                        hv[q] = f32_to_bf16_rne(v[u][q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (gid[q] < 0) {             // not a group's column: its own bits again
+                        hm[q] = __float_as_uint(m[u][q]) >> 16;
+                        hv[q] = __float_as_uint(v[u][q]) >> 16;
+                    }
+                }
+                store_f<4>(S.pk_param + e, th[u]);
+                store_h<4>(static_cast<uint16_t*>(S.pk_m) + e, hm);
+                store_h<4>(static_cast<uint16_t*>(S.pk_v) + e, hv);
+            } else {
+                store_f<4>(S.pk_param + e, th[u]);
+                store_f<4>(static_cast<float*>(S.pk_m) + e, m[u]);
+                store_f<4>(static_cast<float*>(S.pk_v) + e, v[u]);
+            }
+        }
+    }
+}
+
 // Every group's pass over the staged rows.  U: (row, chunk) items per lane
 // per trip for the 16/8-byte groups (twice that for 4-byte ones, the noise
 // group included).
-template <bool BF16, bool NOISE, int U>
+template <bool BF16, bool NOISE, int U, bool PACKED>
 __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H, uint64_t seed, int nrows,
                                                 const int* s_row, const float* s_rb1, const float* s_rsb2,
                                                 int lane, float* s_noise = nullptr)
@@ -521,6 +689,9 @@ __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H
         nz.q = S.g[H.noise_g[2]].param;
         nz.kappa = S.g[H.noise_g[1]].param;
         nz.tau = S.g[H.noise_g[3]].param;
+        nz.sq = S.g[H.noise_g[2]].stride;
+        nz.sk = S.g[H.noise_g[1]].stride;
+        nz.st = S.g[H.noise_g[3]].stride;
         nz.s2 = d_stream(seed, kTagNoise, H.iteration);
         nz.scale = (float)(H.noise_lr * (double)G.lr);
         const float dar_scale = (G.dar_kind != GS_DAR_NONE && G.reg_mode == GS_REG_ADAPTIVE)
@@ -532,7 +703,16 @@ __device__ __forceinline__ void step_all_groups(const KScene& S, const KHyper& H
         for (int j = lane; j < nrows; j += kWave)
             noise_row(nz, (int64_t)(s_row[j] & 0x7FFFFFFF), H.noise_k, H.noise_t, &s_noise[3 * j]);
         wave_sync();
-        step_group<BF16, 1, U * 2, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, s_noise);
+        if (!PACKED || S.pk_stride == 0)
+            step_group<BF16, 1, U * 2, true>(G, H, nrows, s_row, s_rb1, s_rsb2, lane, dar_scale, s2, s_noise);
+    }
+    // the packed pass is compiled only into the kernels for packed scenes, so
+    // the per-group kernels keep their register budget
+    if constexpr (PACKED) {
+        if (S.pk_stride > 0) {
+            step_packed<BF16, U, NOISE>(S, H, seed, nrows, s_row, s_rb1, s_rsb2, lane, s_noise);
+            return;
+        }
     }
     for (int gi = 0; gi < S.n_groups; ++gi) {
         if (gi == first) continue;

@@ -30,7 +30,7 @@ struct KGroup {
     int32_t dar_kind;
     int32_t reg_mode;
     float dar_clip;
-    int32_t pad;
+    int32_t stride;      // elements from one row to the next (>= dim)
     double dar_lambda;   // lambda; the kernels form lambda / N_I' in double, as the host would
 };
 
@@ -71,7 +71,24 @@ struct KScene {
     const int32_t* idx;
     const int32_t* count;
     int32_t* t;
+    // Packed rows: every group is a column range of the same [n][pk_stride]
+    // arrays (pk_param, pk_grad, pk_m, pk_v), pk_stride a power of two in
+    // [4, 256]; the step then takes each row in one pass (set by
+    // plan_packed_rows; pk_stride = 0 otherwise).
+    int32_t pk_stride;
+    int32_t pk_col[GS_MAX_GROUPS];     // first column of each group
+    float* pk_param;
+    const float* pk_grad;
+    void* pk_m;
+    void* pk_v;
 };
+
+// Sets the packed-row fields of a scene whose groups are set (msz: bytes
+// per moment element): packed when all groups share one row stride that is
+// a power of two in [4, 256], lie at the same column in the attribute,
+// gradient and both moment arrays, do not overlap, and the arrays' row
+// starts allow 16-byte attribute and 4-element moment accesses.
+void plan_packed_rows(KScene& s, size_t msz);
 
 struct KCamera {
     float R[12];
@@ -91,12 +108,14 @@ struct KCameras {
 // host-side helpers shared by the library's translation units
 uint64_t splitmix_output(uint64_t s, uint64_t k);
 
-hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
+// means: rows ms elements apart (ms >= 3)
+hipError_t launch_visibility(const float* means, int64_t ms, const float* radius, int64_t n, const KCamera& cam,
                              uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream);
-hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means,
+hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means, int64_t ms,
                             const float* radius, uint8_t* mask_out, hipStream_t stream);
-hipError_t launch_visibility_multi(const float* means, const float* radius, int64_t n, const KCameras& cams,
-                                   uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count, hipStream_t stream);
+hipError_t launch_visibility_multi(const float* means, int64_t ms, const float* radius, int64_t n,
+                                   const KCameras& cams, uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count,
+                                   hipStream_t stream);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, hipStream_t stream);
 // The invisible-row pass (Re-State / AIU samples) runs first when either is on.
 hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream);
@@ -111,7 +130,7 @@ hipError_t launch_batched(const KScene* d_scenes, int32_t n_scenes, const int64_
 
 // relocation
 size_t relocate_workspace_bytes(int64_t n);
-hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene& s, int reset_t,
+hipError_t launch_relocate(const float* key, int64_t key_stride, int64_t n, int64_t k, const KScene& s, int reset_t,
                            int32_t* selected, void* ws, hipStream_t stream);
 
 }  // namespace gs

@@ -37,13 +37,14 @@ __global__ void bbox_init_kernel(uint32_t* box)
     else if (threadIdx.x < 6) box[threadIdx.x] = 0u;
 }
 
-__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ means, int64_t n, uint32_t* box)
+__global__ __launch_bounds__(256) void bbox_kernel(const float* __restrict__ means, int64_t ms, int64_t n,
+                                                   uint32_t* box)
 {
     uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float x = means[3 * i + a];
+            const float x = means[ms * i + a];
             if (x == x) {                      // NaN means take no part in the box
                 const uint32_t o = f2ord(x);
                 lo[a] = min(lo[a], o);
@@ -89,7 +90,7 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x)
     return x;
 }
 
-__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ means, int64_t n,
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ means, int64_t ms, int64_t n,
                                                      const uint32_t* box, uint32_t* __restrict__ keys,
                                                      int32_t* __restrict__ vals)
 {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ m
         uint32_t q[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float t = (means[3 * i + a] - lo[a]) * scale[a];
+            const float t = (means[ms * i + a] - lo[a]) * scale[a];
             q[a] = t >= 0.0f ? (uint32_t)min(t, 1023.0f) : 0u;        // NaN -> 0
         }
         keys[i] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
@@ -145,11 +146,14 @@ extern "C" size_t gs_spatial_order_workspace_size(int64_t n)
     return kAlign + 3 * align_up((size_t)n * 4) + align_up(sort_temp_bytes(n));
 }
 
-extern "C" gs_status gs_spatial_order(const float* means, int64_t n, int32_t* perm, void* workspace,
-                                      size_t workspace_bytes, hipStream_t stream)
+extern "C" gs_status gs_spatial_order(const float* means, int64_t means_stride, int64_t n, int32_t* perm,
+                                      void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
     clear_error();
     if (n < 0 || n >= ((int64_t)1 << 31)) return set_error(GS_EINVAL, "gs_spatial_order: n must be in [0, 2^31)");
+    const int64_t ms = means_stride == 0 ? 3 : means_stride;
+    if (ms < 3 || ms > 65536 || ms * n >= ((int64_t)1 << 40))
+        return set_error(GS_EINVAL, "gs_spatial_order: means_stride must be 0 or in [3, 65536]");
     if (n == 0) return GS_OK;
     if (means == nullptr || perm == nullptr || workspace == nullptr)
         return set_error(GS_EINVAL, "gs_spatial_order: means, perm and workspace are required");
@@ -166,8 +170,8 @@ extern "C" gs_status gs_spatial_order(const float* means, int64_t n, int32_t* pe
     size_t temp_bytes = sort_temp_bytes(n);
     hipLaunchKernelGGL(bbox_init_kernel, dim3(1), dim3(64), 0, stream, box);
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(bbox_kernel, dim3(std::min(grid, 512u)), dim3(256), 0, stream, means, n, box);
-    hipLaunchKernelGGL(morton_kernel, dim3(grid), dim3(256), 0, stream, means, n, box, keys_in, vals_in);
+    hipLaunchKernelGGL(bbox_kernel, dim3(std::min(grid, 512u)), dim3(256), 0, stream, means, ms, n, box);
+    hipLaunchKernelGGL(morton_kernel, dim3(grid), dim3(256), 0, stream, means, ms, n, box, keys_in, vals_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(GS_EHIP, hipGetErrorString(e));
     e = rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, vals_in, perm, (size_t)n, 0, 30, stream);

@@ -34,10 +34,14 @@ constexpr int kMaxArrays = 3 * GS_MAX_GROUPS + 1;
 constexpr size_t kWsAlign = 256;
 
 // One per-primitive array: rows of row_bytes, moved in chunks of w bytes
-// (cpr chunks per row).  src == nullptr: the destination rows are zeroed.
+// (cpr chunks per row); consecutive rows start src_pitch / dst_pitch bytes
+// apart (the row length, or a packed array's row).  src == nullptr: the
+// destination rows are zeroed.
 struct KArr {
     const char* src;
     char* dst;
+    int64_t src_pitch;
+    int64_t dst_pitch;
     int32_t row_bytes;
     int32_t w;
     int32_t cpr;
@@ -88,10 +92,10 @@ __device__ __forceinline__ void move_rows(const KArr& A, int nrows, const int* s
             const bool in = k0 + u * kWave < items;
             const int s = in ? s_src[r] : -1;
             ok[u] = in && (A.src == nullptr || s >= 0);
-            d[u] = (dst0 + r) * (int64_t)A.row_bytes + (int64_t)c * W;
+            d[u] = (dst0 + r) * A.dst_pitch + (int64_t)c * W;
             x[u] = T{};
             if (ok[u] && A.src != nullptr)
-                x[u] = ld<T, NT>(reinterpret_cast<const T*>(A.src + (int64_t)s * A.row_bytes + (int64_t)c * W));
+                x[u] = ld<T, NT>(reinterpret_cast<const T*>(A.src + (int64_t)s * A.src_pitch + (int64_t)c * W));
             r += dr;
             c += dc;
             if (c >= cpr) { c -= cpr; ++r; }
@@ -184,21 +188,27 @@ __global__ __launch_bounds__(kBlock) void append_kernel(KMut M, int64_t units)
 
 size_t align_up(size_t x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
 
-int chunk_width(size_t row_bytes, const void* a, const void* b)
+int chunk_width(size_t row_bytes, size_t sp, size_t dp, const void* a, const void* b)
 {
     for (int w = 16; w >= 2; w /= 2)
-        if (row_bytes % (size_t)w == 0 && (uintptr_t)a % (uintptr_t)w == 0 && (uintptr_t)b % (uintptr_t)w == 0)
+        if (row_bytes % (size_t)w == 0 && sp % (size_t)w == 0 && dp % (size_t)w == 0 &&
+            (uintptr_t)a % (uintptr_t)w == 0 && (uintptr_t)b % (uintptr_t)w == 0)
             return w;
     return 0;
 }
 
-bool add_arr(KMut& M, const void* src, void* dst, size_t row_bytes)
+// src_pitch / dst_pitch 0: the row length
+bool add_arr(KMut& M, const void* src, void* dst, size_t row_bytes, size_t src_pitch = 0, size_t dst_pitch = 0)
 {
-    const int w = chunk_width(row_bytes, src != nullptr ? src : dst, dst);
+    const size_t sp = src_pitch != 0 ? src_pitch : row_bytes;
+    const size_t dp = dst_pitch != 0 ? dst_pitch : row_bytes;
+    const int w = chunk_width(row_bytes, sp, dp, src != nullptr ? src : dst, dst);
     if (w == 0 || M.n_arr >= kMaxArrays) return false;
     KArr& A = M.a[M.n_arr++];
     A.src = static_cast<const char*>(src);
     A.dst = static_cast<char*>(dst);
+    A.src_pitch = (int64_t)sp;
+    A.dst_pitch = (int64_t)dp;
     A.row_bytes = (int32_t)row_bytes;
     A.w = w;
     A.cpr = (int32_t)(row_bytes / (size_t)w);
@@ -213,10 +223,15 @@ gs_status fail_fmt(const char* fmt, int a, int b = 0)
     return set_error(GS_EINVAL, buf);
 }
 
+// elements from one row of a group to the next
+int64_t row_pitch(const gs_group& G) { return G.row_stride != 0 ? G.row_stride : G.dim; }
+
 gs_status check_group(const gs_group& G, int g, int64_t rows, size_t msz, bool need)
 {
     if (G.dim < 1 || G.dim > 4096) return fail_fmt("group %d: dim = %d, must be in [1, 4096]", g, G.dim);
-    if ((int64_t)G.dim * rows >= ((int64_t)1 << 40)) return fail_fmt("group %d: n * dim too large", g);
+    if (G.row_stride != 0 && (G.row_stride < G.dim || G.row_stride > 65536))
+        return fail_fmt("group %d: row_stride = %d, must be 0 or in [dim, 65536]", g, G.row_stride);
+    if (row_pitch(G) * rows >= ((int64_t)1 << 40)) return fail_fmt("group %d: n * row stride too large", g);
     if (need && (G.param == nullptr || G.exp_avg == nullptr || G.exp_avg_sq == nullptr))
         return fail_fmt("group %d: param, exp_avg and exp_avg_sq must be non-NULL", g);
     if ((uintptr_t)G.param % 4 || (uintptr_t)G.exp_avg % msz || (uintptr_t)G.exp_avg_sq % msz)
@@ -279,8 +294,10 @@ extern "C" gs_status gs_prune(const uint8_t* keep, int64_t n, const gs_group* sr
     if (ws == nullptr || ws_bytes < need) return set_error(GS_EINVAL, "gs_prune: workspace smaller than gs_prune_workspace_size(n)");
     for (int g = 0; g < n_groups; ++g) {
         const size_t d = (size_t)src[g].dim;
-        if (!add_arr(M, src[g].param, dst[g].param, d * 4) || !add_arr(M, src[g].exp_avg, dst[g].exp_avg, d * msz) ||
-            !add_arr(M, src[g].exp_avg_sq, dst[g].exp_avg_sq, d * msz))
+        const size_t sp = (size_t)row_pitch(src[g]), dp = (size_t)row_pitch(dst[g]);
+        if (!add_arr(M, src[g].param, dst[g].param, d * 4, sp * 4, dp * 4) ||
+            !add_arr(M, src[g].exp_avg, dst[g].exp_avg, d * msz, sp * msz, dp * msz) ||
+            !add_arr(M, src[g].exp_avg_sq, dst[g].exp_avg_sq, d * msz, sp * msz, dp * msz))
             return set_error(GS_EINVAL, "gs_prune: misaligned rows");
     }
     if (!add_arr(M, t_src, t_dst, 4)) return set_error(GS_EINVAL, "gs_prune: misaligned step counts");
@@ -328,8 +345,10 @@ extern "C" gs_status gs_append(const gs_group* groups, int32_t n_groups, int32_t
     memset(&M, 0, sizeof M);
     for (int g = 0; g < n_groups; ++g) {
         const size_t d = (size_t)groups[g].dim;
-        if (!add_arr(M, groups[g].param, groups[g].param, d * 4) ||
-            !add_arr(M, nullptr, groups[g].exp_avg, d * msz) || !add_arr(M, nullptr, groups[g].exp_avg_sq, d * msz))
+        const size_t p = (size_t)row_pitch(groups[g]);
+        if (!add_arr(M, groups[g].param, groups[g].param, d * 4, p * 4, p * 4) ||
+            !add_arr(M, nullptr, groups[g].exp_avg, d * msz, p * msz, p * msz) ||
+            !add_arr(M, nullptr, groups[g].exp_avg_sq, d * msz, p * msz, p * msz))
             return set_error(GS_EINVAL, "gs_append: misaligned rows");
     }
     if (!add_arr(M, nullptr, step_count, 4)) return set_error(GS_EINVAL, "gs_append: misaligned step counts");

@@ -124,16 +124,17 @@ __device__ SelectState narrow(const SelectState* prev, uint32_t* hist, int pass,
 
 // The block's keys, mapped to order-preserving uint32; entries past n get
 // the largest key and are excluded by the callers through the index test.
-__device__ __forceinline__ void load_keys(const float* __restrict__ key, int64_t n, int64_t first,
+__device__ __forceinline__ void load_keys(const float* __restrict__ key, int64_t ks, int64_t n, int64_t first,
                                           uint32_t (&o)[kRelPerThread])
 {
 #pragma unroll
-    for (int j = 0; j < kRelPerThread; ++j) o[j] = key_ord(key[min(first + (int64_t)j * kBlock + threadIdx.x, n - 1)]);
+    for (int j = 0; j < kRelPerThread; ++j)
+        o[j] = key_ord(key[ks * min(first + (int64_t)j * kBlock + threadIdx.x, n - 1)]);
 }
 
 // Digit pass p (bits 31-8p .. 24-8p): histogram of the keys that match the
 // state narrowed by passes 0 .. p-1.
-__global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t n,
+__global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
                                                              SelectState* st, int pass, uint32_t* hist)
 {
     // one private histogram per wave: keys such as opacity logits fall into
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     for (int w = 0; w < kWavesPerBlock; ++w) s_hist[w][threadIdx.x] = 0u;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[kRelPerThread];
-    load_keys(key, n, first, o);
+    load_keys(key, ks, n, first, o);
     const int shift = 24 - 8 * pass;
     const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist, pass - 1, shift + 8);
     if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
 
 // Per block: keys below K and keys equal to K, K being the key of the k-th
 // smallest (the state after the last pass, recorded in st[4] by block 0).
-__global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __restrict__ key, int64_t n,
+__global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
                                                               SelectState* st, uint32_t* hist, int32_t* lt,
                                                               int32_t* eq)
 {
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __res
     const bool any = fin.rank > 0;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[kRelPerThread];
-    load_keys(key, n, first, o);
+    load_keys(key, ks, n, first, o);
     int nl = 0, ne = 0;
 #pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
@@ -289,7 +290,7 @@ __device__ __forceinline__ void zero_group(const KGroup& G, int nrows, const int
     const float zf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     const uint32_t zh[4] = {0u, 0u, 0u, 0u};
     for (int k = lane; k < items; k += kWave) {
-        const int64_t e = (int64_t)s_row[r] * G.dim + c * V;
+        const int64_t e = (int64_t)s_row[r] * G.stride + c * V;
         if constexpr (BF16) {
             store_h<V>(static_cast<uint16_t*>(G.m) + e, zh);
             store_h<V>(static_cast<uint16_t*>(G.v) + e, zh);
@@ -311,7 +312,7 @@ __device__ __forceinline__ void zero_group(const KGroup& G, int nrows, const int
 // two barriers give every wave its offsets.  INLINE: lt / eq are the
 // per-block counts, summed here; else their exclusive scans.
 template <bool INLINE, bool BF16>
-__global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __restrict__ key, int64_t n,
+__global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
                                                               const SelectState* st, const int32_t* lt,
                                                               const int32_t* eq, int32_t* sel, KScene S,
                                                               int reset_t)
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
     const int lane = threadIdx.x % kWave;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[J];
-    load_keys(key, n, first, o);
+    load_keys(key, ks, n, first, o);
     int lt0, eq0;
     if constexpr (INLINE) {
         counts_before(lt, eq, &lt0, &eq0);
@@ -395,15 +396,15 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
 }
 
 template <bool INLINE>
-void launch_write(int nblocks, hipStream_t stream, const float* key, int64_t n, const SelectState* st,
+void launch_write(int nblocks, hipStream_t stream, const float* key, int64_t ks, int64_t n, const SelectState* st,
                   const int32_t* lt, const int32_t* eq, int32_t* sel, const KScene& s, int reset_t)
 {
     if (s.bf16)
-        hipLaunchKernelGGL((select_write_kernel<INLINE, true>), dim3(nblocks), dim3(kBlock), 0, stream, key, n, st,
-                           lt, eq, sel, s, reset_t);
+        hipLaunchKernelGGL((select_write_kernel<INLINE, true>), dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n,
+                           st, lt, eq, sel, s, reset_t);
     else
-        hipLaunchKernelGGL((select_write_kernel<INLINE, false>), dim3(nblocks), dim3(kBlock), 0, stream, key, n, st,
-                           lt, eq, sel, s, reset_t);
+        hipLaunchKernelGGL((select_write_kernel<INLINE, false>), dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n,
+                           st, lt, eq, sel, s, reset_t);
 }
 
 }  // namespace
@@ -435,8 +436,8 @@ void* scratch_address(hipError_t* err)
     return addr[dev];
 }
 
-hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene& s, int reset_t, int32_t* selected,
-                           void* ws, hipStream_t stream)
+hipError_t launch_relocate(const float* key, int64_t ks, int64_t n, int64_t k, const KScene& s, int reset_t,
+                           int32_t* selected, void* ws, hipStream_t stream)
 {
     const int nblocks = (int)((n + kRelPerBlock - 1) / kRelPerBlock);
     const size_t hist_bytes = align_up(kHistWords * 4);
@@ -448,13 +449,13 @@ hipError_t launch_relocate(const float* key, int64_t n, int64_t k, const KScene&
 
     hipLaunchKernelGGL(select_init_kernel, dim3(4 * kHistCopies), dim3(256), 0, stream, st, hist, (int32_t)k);
     for (int pass = 0; pass < 4; ++pass)
-        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, pass, hist);
-    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, n, st, hist, lt, eq);
+        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, pass, hist);
+    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, hist, lt, eq);
     if (nblocks <= kInlineScanBlocks) {
-        launch_write<true>(nblocks, stream, key, n, st, lt, eq, selected, s, reset_t);
+        launch_write<true>(nblocks, stream, key, ks, n, st, lt, eq, selected, s, reset_t);
     } else {
         hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(kBlock), 0, stream, lt, eq, nblocks);
-        launch_write<false>(nblocks, stream, key, n, st, lt, eq, selected, s, reset_t);
+        launch_write<false>(nblocks, stream, key, ks, n, st, lt, eq, selected, s, reset_t);
     }
     return hipGetLastError();
 }
@@ -474,14 +475,18 @@ extern "C" size_t gs_relocate_workspace_size(int64_t n)
 namespace {
 
 // Host-side checks and group set-up shared by both entry points.
-gs_status relocate_prepare(const char* who, const float* key, int64_t n, int64_t k, const gs_group* groups,
-                           int32_t n_groups, int32_t moment_dtype, int32_t* step_count, int32_t reset_t,
-                           int32_t* selected, KScene* s, bool* empty)
+gs_status relocate_prepare(const char* who, const float* key, int64_t key_stride, int64_t n, int64_t k,
+                           const gs_group* groups, int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
+                           int32_t reset_t, int32_t* selected, KScene* s, bool* empty)
 {
     char msg[160];
     *empty = false;
     if (n < 0 || n >= ((int64_t)1 << 31)) {
         snprintf(msg, sizeof msg, "%s: n must be in [0, 2^31)", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (key_stride < 0 || key_stride > 65536 || key_stride * n >= ((int64_t)1 << 40)) {
+        snprintf(msg, sizeof msg, "%s: key_stride must be 0 or in [1, 65536] (and n * stride < 2^40)", who);
         return set_error(GS_EINVAL, msg);
     }
     if (k < 0 || k > n) {
@@ -521,27 +526,30 @@ gs_status relocate_prepare(const char* who, const float* key, int64_t n, int64_t
 
 }  // namespace
 
-extern "C" gs_status gs_relocate_reset(const float* key, int64_t n, int64_t k, const gs_group* groups,
-                                       int32_t n_groups, int32_t moment_dtype, int32_t* step_count, int32_t reset_t,
-                                       int32_t* selected, void* workspace, size_t workspace_bytes, hipStream_t stream)
+extern "C" gs_status gs_relocate_reset(const float* key, int64_t key_stride, int64_t n, int64_t k,
+                                       const gs_group* groups, int32_t n_groups, int32_t moment_dtype,
+                                       int32_t* step_count, int32_t reset_t, int32_t* selected, void* workspace,
+                                       size_t workspace_bytes, hipStream_t stream)
 {
     clear_error();
     KScene s;
     bool empty = false;
-    gs_status st = relocate_prepare("gs_relocate_reset", key, n, k, groups, n_groups, moment_dtype, step_count,
-                                    reset_t, selected, &s, &empty);
+    gs_status st = relocate_prepare("gs_relocate_reset", key, key_stride, n, k, groups, n_groups, moment_dtype,
+                                    step_count, reset_t, selected, &s, &empty);
     if (st != GS_OK || empty) return st;
     if (workspace == nullptr) return set_error(GS_EINVAL, "gs_relocate_reset: workspace is required");
     if ((uintptr_t)workspace % kAlign)
         return set_error(GS_EINVAL, "gs_relocate_reset: misaligned workspace (needs 256 bytes)");
     if (workspace_bytes < relocate_workspace_bytes(n)) return set_error(GS_EINVAL, "gs_relocate_reset: workspace too small");
-    const hipError_t e = launch_relocate(key, n, k, s, reset_t, selected, workspace, stream);
+    const hipError_t e = launch_relocate(key, key_stride == 0 ? 1 : key_stride, n, k, s, reset_t, selected, workspace,
+                                         stream);
     return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
 }
 
-extern "C" gs_status gs_relocate_reset_noalloc(const float* key, int64_t n, int64_t k, const gs_group* groups,
-                                               int32_t n_groups, int32_t moment_dtype, int32_t* step_count,
-                                               int32_t reset_t, int32_t* selected, hipStream_t stream)
+extern "C" gs_status gs_relocate_reset_noalloc(const float* key, int64_t key_stride, int64_t n, int64_t k,
+                                               const gs_group* groups, int32_t n_groups, int32_t moment_dtype,
+                                               int32_t* step_count, int32_t reset_t, int32_t* selected,
+                                               hipStream_t stream)
 {
     clear_error();
     if (n > GS_RELOCATE_NOALLOC_MAX_N)
@@ -549,12 +557,12 @@ extern "C" gs_status gs_relocate_reset_noalloc(const float* key, int64_t n, int6
                                     "(use gs_relocate_reset with a workspace)");
     KScene s;
     bool empty = false;
-    gs_status st = relocate_prepare("gs_relocate_reset_noalloc", key, n, k, groups, n_groups, moment_dtype,
-                                    step_count, reset_t, selected, &s, &empty);
+    gs_status st = relocate_prepare("gs_relocate_reset_noalloc", key, key_stride, n, k, groups, n_groups,
+                                    moment_dtype, step_count, reset_t, selected, &s, &empty);
     if (st != GS_OK || empty) return st;
     hipError_t e = hipSuccess;
     void* ws = scratch_address(&e);
     if (ws == nullptr) return set_error(GS_EHIP, hipGetErrorString(e));
-    e = launch_relocate(key, n, k, s, reset_t, selected, ws, stream);
+    e = launch_relocate(key, key_stride == 0 ? 1 : key_stride, n, k, s, reset_t, selected, ws, stream);
     return e == hipSuccess ? GS_OK : set_error(GS_EHIP, hipGetErrorString(e));
 }

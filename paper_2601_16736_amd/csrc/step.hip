@@ -19,7 +19,7 @@ namespace gs {
 #define GS_STEP_UNROLL_BF16 2
 #endif
 
-template <bool BF16, int SCHED, int UNIT, bool NOISE>
+template <bool BF16, int SCHED, int UNIT, bool NOISE, bool PACKED>
 __global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
 {
     __shared__ int s_row[kWavesPerBlock][UNIT];
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KScene S, KHyper H)
     stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H, d_stream(seed, kTagRsr, H.iteration),
                     lane);
     wave_sync();
-    step_all_groups<BF16, NOISE, BF16 ? GS_STEP_UNROLL_BF16 : GS_STEP_UNROLL>(S, H, seed, nrows, s_row[wave],
+    step_all_groups<BF16, NOISE, BF16 ? GS_STEP_UNROLL_BF16 : GS_STEP_UNROLL, PACKED>(S, H, seed, nrows, s_row[wave],
                                                                             s_rb1[wave], s_rsb2[wave], lane,
                                                                             s_noise[wave]);
 }
@@ -81,34 +81,34 @@ namespace {
 
 using StepFn = void (*)(KScene, KHyper);
 
-template <bool BF16, bool NOISE>
+template <bool BF16, bool NOISE, bool PACKED>
 StepFn pick(int sched, int unit)
 {
     if (sched == kSchedCompacted) {
         switch (unit) {
-        case 32: return step_kernel<BF16, kSchedCompacted, 32, NOISE>;
-        case 64: return step_kernel<BF16, kSchedCompacted, 64, NOISE>;
-        case 128: return step_kernel<BF16, kSchedCompacted, 128, NOISE>;
-        case 256: return step_kernel<BF16, kSchedCompacted, 256, NOISE>;
-        case 512: return step_kernel<BF16, kSchedCompacted, 512, NOISE>;
+        case 32: return step_kernel<BF16, kSchedCompacted, 32, NOISE, PACKED>;
+        case 64: return step_kernel<BF16, kSchedCompacted, 64, NOISE, PACKED>;
+        case 128: return step_kernel<BF16, kSchedCompacted, 128, NOISE, PACKED>;
+        case 256: return step_kernel<BF16, kSchedCompacted, 256, NOISE, PACKED>;
+        case 512: return step_kernel<BF16, kSchedCompacted, 512, NOISE, PACKED>;
         default: return nullptr;
         }
     }
     if (sched == kSchedMasked) {
         switch (unit) {
-        case 32: return step_kernel<BF16, kSchedMasked, 32, NOISE>;
-        case 64: return step_kernel<BF16, kSchedMasked, 64, NOISE>;
-        case 128: return step_kernel<BF16, kSchedMasked, 128, NOISE>;
-        case 256: return step_kernel<BF16, kSchedMasked, 256, NOISE>;
-        case 512: return step_kernel<BF16, kSchedMasked, 512, NOISE>;
+        case 32: return step_kernel<BF16, kSchedMasked, 32, NOISE, PACKED>;
+        case 64: return step_kernel<BF16, kSchedMasked, 64, NOISE, PACKED>;
+        case 128: return step_kernel<BF16, kSchedMasked, 128, NOISE, PACKED>;
+        case 256: return step_kernel<BF16, kSchedMasked, 256, NOISE, PACKED>;
+        case 512: return step_kernel<BF16, kSchedMasked, 512, NOISE, PACKED>;
         default: return nullptr;
         }
     }
     if (sched == kSchedDense) {
         switch (unit) {
-        case 64: return step_kernel<BF16, kSchedDense, 64, NOISE>;
-        case 256: return step_kernel<BF16, kSchedDense, 256, NOISE>;
-        case 512: return step_kernel<BF16, kSchedDense, 512, NOISE>;
+        case 64: return step_kernel<BF16, kSchedDense, 64, NOISE, PACKED>;
+        case 256: return step_kernel<BF16, kSchedDense, 256, NOISE, PACKED>;
+        case 512: return step_kernel<BF16, kSchedDense, 512, NOISE, PACKED>;
         default: return nullptr;
         }
     }
@@ -129,8 +129,14 @@ hipError_t launch_step(const KScene& s, const KHyper& h, hipStream_t stream)
         const hipError_t e = launch_invisible(s, h, stream);
         if (e != hipSuccess) return e;
     }
-    StepFn fn = s.bf16 ? (h.noise ? pick<true, true>(s.sched, s.unit) : pick<true, false>(s.sched, s.unit))
-                       : (h.noise ? pick<false, true>(s.sched, s.unit) : pick<false, false>(s.sched, s.unit));
+    StepFn fn;
+    if (s.pk_stride > 0)
+        fn = s.bf16 ? (h.noise ? pick<true, true, true>(s.sched, s.unit) : pick<true, false, true>(s.sched, s.unit))
+                    : (h.noise ? pick<false, true, true>(s.sched, s.unit) : pick<false, false, true>(s.sched, s.unit));
+    else
+        fn = s.bf16 ? (h.noise ? pick<true, true, false>(s.sched, s.unit) : pick<true, false, false>(s.sched, s.unit))
+                    : (h.noise ? pick<false, true, false>(s.sched, s.unit)
+                               : pick<false, false, false>(s.sched, s.unit));
     if (fn == nullptr) return hipErrorInvalidValue;
     const size_t units = step_kernel_units(s);
     const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);

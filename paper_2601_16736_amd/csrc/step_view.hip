@@ -29,9 +29,9 @@ __device__ __forceinline__ bool visible_any(float x, float y, float z, const flo
     return v;
 }
 
-template <bool BF16, int UNIT, bool NOISE, bool RADIUS, typename CAMS>
+template <bool BF16, int UNIT, bool NOISE, bool RADIUS, bool PACKED, typename CAMS>
 __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, CAMS cam,
-                                                           const float* __restrict__ means,
+                                                           const float* __restrict__ means, int64_t ms,
                                                            const float* __restrict__ radius,
                                                            uint8_t* __restrict__ mask_out)
 {
@@ -52,9 +52,9 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
 #pragma unroll
     for (int b = 0; b < R; ++b) {
         const int64_t i = min(w0 + b * kWave + lane, S.n - 1);
-        x[b] = means[3 * i];
-        y[b] = means[3 * i + 1];
-        z[b] = means[3 * i + 2];
+        x[b] = means[ms * i];
+        y[b] = means[ms * i + 1];
+        z[b] = means[ms * i + 2];
         rho[b] = RADIUS ? radius[i] : 0.0f;
     }
     bool vis[R], in[R];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
         stage_step_rows(nrows, s_row[wave], s_rb1[wave], s_rsb2[wave], S.t, H,
                         d_stream(seed, kTagRsr, H.iteration), lane);
         wave_sync();
-        step_all_groups<BF16, NOISE, BF16 ? GS_STEP_UNROLL_BF16 : GS_STEP_UNROLL>(S, H, seed, nrows, s_row[wave],
+        step_all_groups<BF16, NOISE, BF16 ? GS_STEP_UNROLL_BF16 : GS_STEP_UNROLL, PACKED>(S, H, seed, nrows, s_row[wave],
                                                                                   s_rb1[wave], s_rsb2[wave], lane,
                                                                                   s_noise[wave]);
     }
@@ -121,52 +121,55 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
 namespace {
 
 template <typename CAMS>
-using ViewFn = void (*)(KScene, KHyper, CAMS, const float*, const float*, uint8_t*);
+using ViewFn = void (*)(KScene, KHyper, CAMS, const float*, int64_t, const float*, uint8_t*);
 
-template <bool BF16, bool NOISE, bool RADIUS, typename CAMS>
+template <bool BF16, bool NOISE, bool RADIUS, bool PACKED, typename CAMS>
 ViewFn<CAMS> pick_view(int unit)
 {
     switch (unit) {
-    case 32: return step_view_kernel<BF16, 32, NOISE, RADIUS, CAMS>;
-    case 64: return step_view_kernel<BF16, 64, NOISE, RADIUS, CAMS>;
-    case 128: return step_view_kernel<BF16, 128, NOISE, RADIUS, CAMS>;
-    case 256: return step_view_kernel<BF16, 256, NOISE, RADIUS, CAMS>;
+    case 32: return step_view_kernel<BF16, 32, NOISE, RADIUS, PACKED, CAMS>;
+    case 64: return step_view_kernel<BF16, 64, NOISE, RADIUS, PACKED, CAMS>;
+    case 128: return step_view_kernel<BF16, 128, NOISE, RADIUS, PACKED, CAMS>;
+    case 256: return step_view_kernel<BF16, 256, NOISE, RADIUS, PACKED, CAMS>;
     default: return nullptr;
     }
 }
 
-template <typename CAMS>
+template <bool PACKED, typename CAMS>
 ViewFn<CAMS> pick_view(bool bf16, int unit, bool noise, bool radius)
 {
     if (bf16) {
-        if (noise) return radius ? pick_view<true, true, true, CAMS>(unit) : pick_view<true, true, false, CAMS>(unit);
-        return radius ? pick_view<true, false, true, CAMS>(unit) : pick_view<true, false, false, CAMS>(unit);
+        if (noise)
+            return radius ? pick_view<true, true, true, PACKED, CAMS>(unit) : pick_view<true, true, false, PACKED, CAMS>(unit);
+        return radius ? pick_view<true, false, true, PACKED, CAMS>(unit) : pick_view<true, false, false, PACKED, CAMS>(unit);
     }
-    if (noise) return radius ? pick_view<false, true, true, CAMS>(unit) : pick_view<false, true, false, CAMS>(unit);
-    return radius ? pick_view<false, false, true, CAMS>(unit) : pick_view<false, false, false, CAMS>(unit);
+    if (noise)
+        return radius ? pick_view<false, true, true, PACKED, CAMS>(unit) : pick_view<false, true, false, PACKED, CAMS>(unit);
+    return radius ? pick_view<false, false, true, PACKED, CAMS>(unit) : pick_view<false, false, false, PACKED, CAMS>(unit);
 }
 
 template <typename CAMS>
-hipError_t launch_view(const KScene& s, const KHyper& h, const CAMS& cams, const float* means, const float* radius,
-                       uint8_t* mask_out, hipStream_t stream)
+hipError_t launch_view(const KScene& s, const KHyper& h, const CAMS& cams, const float* means, int64_t ms,
+                       const float* radius, uint8_t* mask_out, hipStream_t stream)
 {
     if (s.n == 0) return hipSuccess;
-    ViewFn<CAMS> fn = pick_view<CAMS>(s.bf16 != 0, s.unit, h.noise != 0, radius != nullptr);
+    ViewFn<CAMS> fn = s.pk_stride > 0 ? pick_view<true, CAMS>(s.bf16 != 0, s.unit, h.noise != 0, radius != nullptr)
+                                      : pick_view<false, CAMS>(s.bf16 != 0, s.unit, h.noise != 0, radius != nullptr);
     if (fn == nullptr) return hipErrorInvalidValue;
     const int64_t units = (s.n + s.unit - 1) / s.unit;
     const unsigned blocks = (unsigned)((units + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, s, h, cams, means, radius, mask_out);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, s, h, cams, means, ms, radius, mask_out);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // One camera: the camera itself is the kernel argument; several: the batch.
-hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means,
+hipError_t launch_step_view(const KScene& s, const KHyper& h, const KCameras& cams, const float* means, int64_t ms,
                             const float* radius, uint8_t* mask_out, hipStream_t stream)
 {
-    if (cams.n == 1) return launch_view(s, h, cams.c[0], means, radius, mask_out, stream);
-    return launch_view(s, h, cams, means, radius, mask_out, stream);
+    if (cams.n == 1) return launch_view(s, h, cams.c[0], means, ms, radius, mask_out, stream);
+    return launch_view(s, h, cams, means, ms, radius, mask_out, stream);
 }
 
 }  // namespace gs

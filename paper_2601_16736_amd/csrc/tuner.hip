@@ -111,6 +111,7 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
         K.dim = dims[g];
         K.vec = dims[g] % 4 == 0 ? 4 : (dims[g] % 2 == 0 ? 2 : 1);
         K.cpr = dims[g] / K.vec;
+        K.stride = dims[g];
         K.lr = 1e-3f;
     }
     DevBuf& bt = bufs[(size_t)n_groups * 4];

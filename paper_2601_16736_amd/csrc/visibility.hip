@@ -57,7 +57,7 @@ __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int6
 }
 
 template <bool RADIUS>
-__global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restrict__ means,
+__global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restrict__ means, int64_t ms,
                                                             const float* __restrict__ radius, int64_t n,
                                                             KCamera cam, uint8_t* __restrict__ mask,
                                                             int32_t* __restrict__ idx, int32_t* count)
@@ -69,9 +69,9 @@ __global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restr
 #pragma unroll
     for (int s = 0; s < kVisRounds; ++s) {
         const int64_t i = min(first + s * kBlock + threadIdx.x, n - 1);
-        x[s] = means[3 * i];
-        y[s] = means[3 * i + 1];
-        z[s] = means[3 * i + 2];
+        x[s] = means[ms * i];
+        y[s] = means[ms * i + 1];
+        z[s] = means[ms * i + 2];
         rho[s] = RADIUS ? radius[i] : 0.0f;
     }
     bool vis[kVisRounds];
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void visibility_kernel(const float* __restr
 // view v; the union (any bit) feeds the mask and the index list.  The means
 // are read once for all views.
 template <bool RADIUS>
-__global__ __launch_bounds__(kBlock) void visibility_multi_kernel(const float* __restrict__ means,
+__global__ __launch_bounds__(kBlock) void visibility_multi_kernel(const float* __restrict__ means, int64_t ms,
                                                                   const float* __restrict__ radius, int64_t n,
                                                                   KCameras cams, uint8_t* __restrict__ mask,
                                                                   uint32_t* __restrict__ bits,
@@ -105,9 +105,9 @@ __global__ __launch_bounds__(kBlock) void visibility_multi_kernel(const float* _
 #pragma unroll
     for (int s = 0; s < kVisRounds; ++s) {
         const int64_t i = min(first + s * kBlock + threadIdx.x, n - 1);
-        x[s] = means[3 * i];
-        y[s] = means[3 * i + 1];
-        z[s] = means[3 * i + 2];
+        x[s] = means[ms * i];
+        y[s] = means[ms * i + 1];
+        z[s] = means[ms * i + 2];
         rho[s] = RADIUS ? radius[i] : 0.0f;
     }
     uint32_t b[kVisRounds];
@@ -152,7 +152,7 @@ __global__ void clear_count_kernel(int32_t* count)
     if (threadIdx.x == 0) count[0] = 0;
 }
 
-hipError_t launch_visibility(const float* means, const float* radius, int64_t n, const KCamera& cam,
+hipError_t launch_visibility(const float* means, int64_t ms, const float* radius, int64_t n, const KCamera& cam,
                              uint8_t* mask, int32_t* idx, int32_t* count, hipStream_t stream)
 {
     if (idx != nullptr) {
@@ -163,11 +163,11 @@ hipError_t launch_visibility(const float* means, const float* radius, int64_t n,
     if (n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
     if (radius != nullptr)
-        hipLaunchKernelGGL(visibility_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam,
-                           mask, idx, count);
+        hipLaunchKernelGGL(visibility_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, ms, radius, n,
+                           cam, mask, idx, count);
     else
-        hipLaunchKernelGGL(visibility_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n, cam,
-                           mask, idx, count);
+        hipLaunchKernelGGL(visibility_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, ms, radius, n,
+                           cam, mask, idx, count);
     return hipGetLastError();
 }
 
@@ -181,8 +181,9 @@ hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_visibility_multi(const float* means, const float* radius, int64_t n, const KCameras& cams,
-                                   uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count, hipStream_t stream)
+hipError_t launch_visibility_multi(const float* means, int64_t ms, const float* radius, int64_t n,
+                                   const KCameras& cams, uint8_t* mask, uint32_t* bits, int32_t* idx, int32_t* count,
+                                   hipStream_t stream)
 {
     if (idx != nullptr) {
         hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kWave), 0, stream, count);
@@ -192,11 +193,11 @@ hipError_t launch_visibility_multi(const float* means, const float* radius, int6
     if (n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + kVisPerBlock - 1) / kVisPerBlock);
     if (radius != nullptr)
-        hipLaunchKernelGGL(visibility_multi_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n,
-                           cams, mask, bits, idx, count);
+        hipLaunchKernelGGL(visibility_multi_kernel<true>, dim3(blocks), dim3(kBlock), 0, stream, means, ms, radius,
+                           n, cams, mask, bits, idx, count);
     else
-        hipLaunchKernelGGL(visibility_multi_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, radius, n,
-                           cams, mask, bits, idx, count);
+        hipLaunchKernelGGL(visibility_multi_kernel<false>, dim3(blocks), dim3(kBlock), 0, stream, means, ms, radius,
+                           n, cams, mask, bits, idx, count);
     return hipGetLastError();
 }
 

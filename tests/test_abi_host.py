@@ -45,7 +45,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_version_and_reg_norm():
-    assert gs.version() == 1
+    assert gs.version() == 2
     for n_i in (1e6, 1089480, 404301, 999999, 10, 7, 0.5):
         assert gs.gs_reg_norm(n_i) == oracle.reg_norm(n_i)
 
@@ -306,3 +306,50 @@ def test_relocate_entry_points_reject_bad_arguments():
     assert gs.GS_RELOCATE_NOALLOC_MAX_N == 1 << 27
     # n = 0 is a no-op that reads no other argument
     gs.gs_relocate_reset_noalloc(_Fake(0, (0,)), 0, [], 0, 0, False, stream=0)
+
+
+def test_row_strides_are_validated():
+    """Strided rows: a group's row_stride must be 0 (contiguous) or cover its
+    dim, within the row-stride limit; a means or key stride must be 0 or
+    large enough for its row.  Every call here fails before any launch."""
+    for rs in (-1, 2, 65537):
+        assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), row_stride=rs)]).status == gs.GS_EINVAL
+    assert _step(groups=[_group(param=_Fake(FAKE, (10, 3)), row_stride=2**16)], n=2**25).status == gs.GS_EINVAL
+    cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
+
+    class Strided(_Fake):
+        def __init__(self, addr, shape, strides):
+            super().__init__(addr, shape)
+            self._s = strides
+
+        def stride(self, i=None):
+            return self._s if i is None else self._s[i]
+
+    for bad in ((2, 1), (70000, 1)):
+        means = Strided(FAKE, (10, 3), bad)
+        with pytest.raises(gs.GsError) as e:
+            gs.gs_visibility(means, cam, mask=FAKE + 4096, stream=0)
+        assert e.value.status == gs.GS_EINVAL and "means_stride" in str(e.value)
+        with pytest.raises(gs.GsError):
+            gs.adamw_gs_step_view([_group(param=_Fake(FAKE, (10, 3)))], 10, FAKE + 65536, gs.StepConfig(), means,
+                                  cam, stream=0)
+        with pytest.raises(gs.GsError):
+            gs.gs_visibility_multi(means, [cam], mask=FAKE + 4096, stream=0)
+    with pytest.raises(ValueError):                     # rows must have unit element stride
+        gs.gs_visibility(Strided(FAKE, (10, 3), (6, 2)), cam, mask=FAKE + 4096, stream=0)
+    ws = _Fake(FAKE + (1 << 24), (1 << 20,))
+    ws.numel, ws.element_size = (lambda: 1 << 20), (lambda: 1)
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_spatial_order(Strided(FAKE, (10, 3), (2, 1)), FAKE + 65536, ws, stream=0)
+    assert e.value.status == gs.GS_EINVAL
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_relocate_reset(Strided(FAKE, (10,), (70000,)), 1, [_group(param=_Fake(FAKE, (10, 3)))], 0,
+                             FAKE + 65536, True, ws, stream=0)
+    assert e.value.status == gs.GS_EINVAL
+    # a group's tensors must agree on their row stride
+    g = gs.Group(Strided(FAKE, (10, 3), (64, 1)), Strided(FAKE + 4096, (10, 3), (3, 1)), FAKE + 8192,
+                 FAKE + 12288, 1e-3)
+    with pytest.raises(ValueError):
+        g.to_c()
+    assert gs.Group(Strided(FAKE, (10, 3), (64, 1)), Strided(FAKE + 4096, (10, 3), (64, 1)), FAKE + 8192,
+                    FAKE + 12288, 1e-3).to_c().row_stride == 64
