@@ -252,15 +252,18 @@ PROBE_SHAPES = [(w, it, ntl, nts, b) for w in (16, 8) for it in (2, 4, 8, 16) fo
                 for b in (0, 1024, 2048)]
 
 
-def stream_ceilings(torch, nbytes: int = 256 << 20, reps: int = 20, shapes=None, stagger: int = 0) -> dict:
+def stream_ceilings(torch, nbytes: int = 1 << 30, reps: int = 20, shapes=None, stagger: int = 0) -> dict:
     """Bandwidth of plain contiguous kernels on this device (bench_probe):
     the step's 4-read / 3-write mix over four arrays of `nbytes`, a copy and
     a read, each timed with HIP events over `reps` launches after 3 untimed
     ones, for every launch shape in `shapes` (access width, accesses in
     flight per thread, non-temporal hints on loads / stores, one-shot or
     resident grid).  Reports the fixed default shape and the best shape of
-    each mix.  Four arrays of 256 MiB exceed the 256 MB Infinity Cache, so
-    every pass streams from HBM.  stagger = 0: four separate allocations;
+    each mix.  Each array is 1 GiB by default, four times the 256 MB
+    Infinity Cache: with 256 MiB arrays, an array loaded without the
+    non-temporal hint stays partly in that cache from one launch to the
+    next, and such shapes then read above what the HBM delivers.
+    stagger = 0: four separate allocations;
     > 0: one allocation holding array k at offset k * (nbytes + stagger),
     so the arrays' element i sit at different offsets modulo any power of
     two up to stagger's lowest set bit."""
@@ -911,7 +914,7 @@ def run_profile_set(gs, torch, reps: int = 10) -> dict:
     FP32 moments, `reps` with BF16 moments, `reps` / 2 dense steps (every
     primitive visible, windows of 64) with FP32 moments; then the streaming
     probes' 4-read / 3-write mix in its default and best swept shapes and the
-    copy in its best shape, `reps` launches each over 4 x 256 MiB.  Each
+    copy in its best shape, `reps` launches each over 4 x 1 GiB.  Each
     kernel is told apart by its name (template arguments) in the trace."""
     import ctypes
 
@@ -956,15 +959,15 @@ def run_profile_set(gs, torch, reps: int = 10) -> dict:
     del params, grads, means
     torch.cuda.empty_cache()
     lib = bench_probe.load()
-    nbytes = 256 << 20
+    nbytes = 1 << 30
     arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
     ptr = [a.data_ptr() for a in arrs]
     sp = ctypes.c_void_p(stream.cuda_stream)
-    for (w, it, ntl, nts) in ((16, 4, 1, 1), (8, 4, 1, 1)):
+    for (w, it, ntl, nts) in ((16, 4, 1, 1), (8, 2, 1, 1)):
         for _ in range(reps):
             lib.gsprobe_rmw_4r3w_cfg(ptr[0], ptr[1], ptr[2], ptr[3], nbytes // 16, w, it, ntl, nts, 0, sp)
     for _ in range(reps):
-        lib.gsprobe_copy_cfg(ptr[0], ptr[1], nbytes // 16, 8, 4, 0, 1, 0, sp)
+        lib.gsprobe_copy_cfg(ptr[0], ptr[1], nbytes // 16, 8, 2, 1, 1, 0, sp)
     torch.cuda.synchronize()
     out["probe"] = reps
     return out
@@ -1224,7 +1227,9 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--device-warmup", type=float, default=1.0,
                     help="seconds of discarded fused steps before anything is timed (device clocks)")
-    ap.add_argument("--probe-mib", type=int, default=256,
+    ap.add_argument("--probe-trips", action="store_true",
+                    help="only the streaming probe's 4-read / 3-write mix with 1 to 256 tiles per block")
+    ap.add_argument("--probe-mib", type=int, default=1024,
                     help="with --probe-sweep: MiB per probe array (4 arrays; the Infinity Cache holds 256 MB)")
     ap.add_argument("--profile-set", action="store_true",
                     help="only a short fixed sequence of step and probe launches, for counter runs")
@@ -1257,6 +1262,20 @@ def main(argv=None) -> int:
         import torch
         import paper_2601_16736_amd as gs
         print(json.dumps(run_profile_set(gs, torch)), flush=True)
+        return 0
+    if args.probe_trips:
+        import torch
+        # the step's mix in its best shapes, with each block taking 1, 2, 4, ...
+        # tiles one after another (one-shot grid = 1 tile per block)
+        nbytes = args.probe_mib << 20
+        shapes = []
+        for (w, it) in ((8, 2), (16, 4)):
+            tiles = (nbytes // w) // (256 * it)
+            shapes += [(w, it, 1, 1, 0)] + [(w, it, 1, 1, tiles // k) for k in (2, 4, 8, 16, 64, 256)]
+        out = stream_ceilings(torch, nbytes=nbytes, shapes=shapes)
+        out["tiles_per_block"] = {f"w{w}_i{it}_b{b}": (1 if b == 0 else ((nbytes // w) // (256 * it)) // b)
+                                  for (w, it, _, _, b) in shapes}
+        print(json.dumps(out), flush=True)
         return 0
     if args.probe_sweep:
         import torch
@@ -1447,7 +1466,7 @@ def main(argv=None) -> int:
         ceil.pop("table")
         ceil["step_frac_of_rmw_4r3w"] = head["achieved_GBps"] / ceil["rmw_4r3w_GBps"]
         ceil["step_frac_of_rmw_4r3w_best"] = head["achieved_GBps"] / ceil["rmw_4r3w_best_GBps"]
-        ceil["kind"] = ("plain contiguous kernels over 4 x 256 MiB arrays (bench_probe); *_GBps: 16-byte "
+        ceil["kind"] = ("plain contiguous kernels over 4 x 1 GiB arrays (bench_probe); *_GBps: 16-byte "
                         "non-temporal accesses, 4 in flight per thread, one tile per block; *_best_GBps: the "
                         "fastest of the swept launch shapes (width, in flight, hints, grid form)")
     out["stream_ceiling"] = ceil

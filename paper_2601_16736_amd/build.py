@@ -25,6 +25,10 @@ COMPILE_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a multiply and an add fuse only where one expression of the source
+    # holds both, so an element's bits do not depend on the code around the
+    # inlined update (the per-group and the packed passes agree bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
