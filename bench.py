@@ -331,6 +331,78 @@ def stream_ceilings(torch, nbytes: int = 1 << 30, reps: int = 20, shapes=None, s
     return out
 
 
+ROWS_PROBE_SHAPES = [(w, it) for w in (32, 64, 128, 256) for it in (2, 4, 8)]
+
+
+def rows_ceiling(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 50, warmup: int = 5,
+                 shapes=None) -> dict:
+    """The masked step's own access pattern with no method arithmetic
+    (bench_probe rows_kernel): per step, gs_visibility writes the camera's
+    mask (not timed), then the probe reads and writes exactly the rows and
+    bytes the masked FP32 step does (the five groups' four arrays, the step
+    counters), timed with HIP events, for each launch shape (window of
+    primitives per wave, chunk items in flight per lane) in `shapes`.  Same
+    accounting as the step: BYTES_PER_VISIBLE per visible row plus 1 B of
+    mask per primitive.  The ratio of a step kernel's bandwidth to the best
+    shape's is how close it comes to what its access pattern allows."""
+    import ctypes
+
+    import bench_probe
+    import synth
+    shapes = list(shapes or ROWS_PROBE_SHAPES)
+    dev = torch.device(DEVICE)
+    lib = bench_probe.load()
+    arrs = []
+    for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads):
+        arrs.append((p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p)))
+    t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    total = warmup + steps
+    counts = torch.zeros(total, dtype=torch.int32, device=dev)
+    ng = len(arrs)
+    ptrs = [(ctypes.c_void_p * ng)(*[a[k].data_ptr() for a in arrs]) for k in range(4)]
+    dims = (ctypes.c_int32 * ng)(*[a[0].shape[1] for a in arrs])
+    gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    means = sd.params[0]
+    table = {}
+    nv = None
+    for (win, items) in shapes:
+        ev = TimingEvents(steps)
+        for k in range(total):
+            gs.gs_visibility(means, gcams[order[k % len(order)]], mask=mask, vis_idx=idx,
+                             vis_count=counts[k:k + 1], stream=stream)
+            j = k - warmup
+            if j >= 0:
+                ev.record("start", j, stream)
+            rc = lib.gsprobe_rows_4r3w_cfg(ctypes.c_void_p(mask.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                           ptrs[0], ptrs[1], ptrs[2], ptrs[3], dims, ng, N_PRIMS, win, items, sp)
+            if rc != 0:
+                raise RuntimeError(f"gsprobe_rows_4r3w_cfg returned {rc}")
+            if j >= 0:
+                ev.record("end", j, stream)
+        torch.cuda.synchronize()
+        durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+        ev.close()
+        nv = counts.cpu().numpy().astype(np.int64)[warmup:]
+        byts = nv * BYTES_PER_VISIBLE["f32"] + N_PRIMS * BYTES_PER_PRIMITIVE["two_launch"]
+        table[f"win{win}_i{items}"] = {"GBps": float(byts.sum() / durs.sum()) / 1e9, "us": float(durs.mean() * 1e6)}
+    del arrs, t, mask, idx
+    torch.cuda.empty_cache()
+    best = max(table, key=lambda k: table[k]["GBps"])
+    step_shape = "win32_i4"
+    return {"GBps": table[step_shape]["GBps"] if step_shape in table else None,
+            "us": table[step_shape]["us"] if step_shape in table else None,
+            "best_GBps": table[best]["GBps"], "best_shape": best, "table": table,
+            "visible_mean": float(nv.mean()), "steps": steps,
+            "kind": "masked-step access pattern without arithmetic (bench_probe rows_kernel): the five groups' "
+                    "attribute, gradient and moment arrays and the step counters; GBps: the step's shape "
+                    "(windows of 32, 4 chunk items in flight); best: fastest of windows 32-256 x 2-8 items; "
+                    "1660 B per visible + 1 B of mask per primitive"}
+
+
 def gpu_clocks():
     """Current GPU clock levels from the amdgpu driver's sysfs files (the run
     does not pin them), or None where they cannot be read.  Plain file
@@ -1227,6 +1299,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--device-warmup", type=float, default=1.0,
                     help="seconds of discarded fused steps before anything is timed (device clocks)")
+    ap.add_argument("--rows-probe", action="store_true",
+                    help="only the two-launch FP32 step and the rows probe (its access pattern, no arithmetic)")
     ap.add_argument("--probe-trips", action="store_true",
                     help="only the streaming probe's 4-read / 3-write mix with 1 to 256 tiles per block")
     ap.add_argument("--probe-mib", type=int, default=1024,
@@ -1262,6 +1336,24 @@ def main(argv=None) -> int:
         import torch
         import paper_2601_16736_amd as gs
         print(json.dumps(run_profile_set(gs, torch)), flush=True)
+        return 0
+    if args.rows_probe:
+        import torch
+        import paper_2601_16736_amd as gs
+        import synth
+        scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
+        cams = synth.camera_rig()
+        order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
+        sd = SceneOnDevice(gs, torch, scene, args.order)
+        device_warmup(gs, torch, sd, cams, seconds=args.device_warmup)
+        two = run_steps(gs, torch, sd, cams, order, "f32", args.steps, args.warmup)
+        two.pop("counts")
+        two.pop("state")
+        rows = rows_ceiling(gs, torch, sd, cams, order, steps=args.steps, warmup=args.warmup)
+        rows["two_launch_step_GBps"] = two["achieved_GBps"]
+        rows["two_launch_step_us"] = two["step_kernel_us"]
+        rows["two_launch_step_frac_of_best"] = two["achieved_GBps"] / rows["best_GBps"]
+        print(json.dumps(rows), flush=True)
         return 0
     if args.probe_trips:
         import torch
@@ -1338,6 +1430,7 @@ def main(argv=None) -> int:
     order = synth.camera_order(len(cams), args.warmup + args.steps, seed=0)
 
     layouts = {args.order: SceneOnDevice(gs, torch, scene, args.order)}
+    layouts_head = layouts[args.order]
     print(f"bench: device warm-up ({args.device_warmup:.1f} s of discarded steps)", file=sys.stderr, flush=True)
     warm_steps = device_warmup(gs, torch, layouts[args.order], cams, seconds=args.device_warmup)
     # the two-launch path (gs_visibility, then the masked step) always runs
@@ -1348,6 +1441,7 @@ def main(argv=None) -> int:
     two = run_steps(gs, torch, layouts[args.order], cams, order, args.moments, args.steps, args.warmup,
                     path="two_launch", keep_state=args.path == "view")
     two_counts = two.pop("counts")
+    two_frac_src = two
     variants = []
     same_as_two_launch = None
     if args.path == "view":
@@ -1469,6 +1563,13 @@ def main(argv=None) -> int:
         ceil["kind"] = ("plain contiguous kernels over 4 x 1 GiB arrays (bench_probe); *_GBps: 16-byte "
                         "non-temporal accesses, 4 in flight per thread, one tile per block; *_best_GBps: the "
                         "fastest of the swept launch shapes (width, in flight, hints, grid form)")
+    if args.moments == "f32":
+        rows = guarded("rows probe", rows_ceiling, gs, torch, layouts_head, cams, order)
+        if "error" not in rows:
+            rows["two_launch_step_frac_of_best"] = two_frac_src["achieved_GBps"] / rows["best_GBps"]
+            rows["fused_step_frac_of_best"] = head["achieved_GBps"] / rows["best_GBps"]
+        if isinstance(ceil, dict):
+            ceil["rows"] = rows
     out["stream_ceiling"] = ceil
     out["gpu_clocks"] = gpu_clocks()
     if not args.no_cpu_baseline:

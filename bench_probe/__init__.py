@@ -37,4 +37,8 @@ def load():
     lib.gsprobe_rmw_4r3w_cfg.argtypes = [vp, vp, vp, vp, i64, i32, i32, i32, i32, i32, vp]
     lib.gsprobe_copy_cfg.argtypes = [vp, vp, i64, i32, i32, i32, i32, i32, vp]
     lib.gsprobe_read_cfg.argtypes = [vp, i64, vp, i32, i32, i32, i32, vp]
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.gsprobe_rows_4r3w.argtypes = [vp, vp, pp, pp, pp, pp, ctypes.POINTER(ctypes.c_int32), i32, i64, vp]
+    lib.gsprobe_rows_4r3w_cfg.argtypes = [vp, vp, pp, pp, pp, pp, ctypes.POINTER(ctypes.c_int32), i32, i64, i32, i32,
+                                          vp]
     return lib

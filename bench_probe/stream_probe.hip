@@ -5,7 +5,8 @@
 // Measurement support only: built as a library of its own, never linked
 // into libgsopt.
 //
-// Three access mixes over 16-byte-aligned arrays:
+// Three access mixes over 16-byte-aligned arrays (and, further down, the
+// masked step's own pattern of rows):
 //   rmw_4r3w  four arrays read (parameter, gradient, two moments), three
 //             written back (parameter, two moments): the step's mix;
 //   copy      one array read, one written;
@@ -105,6 +106,122 @@ __global__ __launch_bounds__(kThreads) void read_kernel(const T* src, int64_t n,
     if (s.x == -1.0e30f) sink[0] = s.y;
 }
 
+// ---------------------------------------------------------------- rows
+// The masked step's access pattern without its arithmetic.  Each wave takes
+// a window of primitives (32 in the step's shape) and keeps, in order, those
+// whose mask byte is set; it bumps their 4-byte counters, then passes over
+// each group: its lanes walk the kept rows' (row, chunk) items, a chunk
+// being 4 floats when the group's width is a multiple of 4 and 1 float
+// otherwise, and each lane issues the loads of its items (attribute,
+// gradient and two moments; U chunk items or 2U single ones in flight)
+// before it writes three back.
+// 16-byte accesses carry the non-temporal hint, 4-byte ones do not.  The
+// values written are plain blends of the ones read.
+constexpr int kRowsWaves = 4;
+constexpr int kMaxRowGroups = 8;
+
+struct RowsArgs {
+    const uint8_t* mask;
+    int32_t* t;
+    float* p[kMaxRowGroups];
+    const float* g[kMaxRowGroups];
+    float* m[kMaxRowGroups];
+    float* v[kMaxRowGroups];
+    int32_t dim[kMaxRowGroups];
+    int32_t n_groups;
+    int64_t n;
+};
+
+template <typename T, int V, int U>
+__device__ __forceinline__ void rows_group(float* P, const float* G, float* M, float* W, int dim, const int* rows,
+                                           int nrows, int lane)
+{
+    constexpr bool NT = V == 4;
+    const int cpr = dim / V;
+    const int items = nrows * cpr;
+    int r = lane / cpr, c = lane - (lane / cpr) * cpr;
+    const int dr = 64 / cpr, dc = 64 - (64 / cpr) * cpr;
+    for (int k0 = lane; k0 < items; k0 += U * 64) {
+        T a[U], b[U], x[U], y[U];
+        int64_t e[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = k0 + u * 64 < items;
+            e[u] = ok[u] ? ((int64_t)rows[r] * dim + c * V) / V : 0;
+            if (ok[u]) {
+                a[u] = ld<NT>(reinterpret_cast<const T*>(P) + e[u]);
+                b[u] = ld<NT>(reinterpret_cast<const T*>(G) + e[u]);
+                x[u] = ld<NT>(reinterpret_cast<const T*>(M) + e[u]);
+                y[u] = ld<NT>(reinterpret_cast<const T*>(W) + e[u]);
+            }
+            r += dr;
+            c += dc;
+            if (c >= cpr) {
+                c -= cpr;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const T mm = 0.875f * x[u] + 0.125f * b[u];
+            st<NT>(a[u] - 0.0625f * mm, reinterpret_cast<T*>(P) + e[u]);
+            st<NT>(mm, reinterpret_cast<T*>(M) + e[u]);
+            st<NT>(0.5f * y[u] + 0.5f * b[u] * b[u], reinterpret_cast<T*>(W) + e[u]);
+        }
+    }
+}
+
+template <int WIN, int U>
+__global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs A)
+{
+    constexpr int R = (WIN + 63) / 64;
+    __shared__ int s_row[kRowsWaves][WIN];
+    const int wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int64_t w0 = ((int64_t)blockIdx.x * kRowsWaves + wave) * WIN;
+    if (w0 >= A.n) return;
+    int nrows = 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+        const int j = b * 64 + lane;
+        const int64_t i = w0 + j;
+        const bool keep = j < WIN && i < A.n && A.mask[i] != 0;
+        const uint64_t bal = __ballot(keep);
+        if (keep) s_row[wave][nrows + __popcll(bal & ((1ull << lane) - 1))] = (int)i;
+        nrows += __popcll(bal);
+    }
+    if (nrows == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = lane; j < nrows; j += 64) {
+        const int row = s_row[wave][j];
+        A.t[row] = A.t[row] + 1;
+    }
+    for (int gi = 0; gi < A.n_groups; ++gi) {
+        if (A.dim[gi] % 4 == 0)
+            rows_group<f4, 4, U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
+        else
+            rows_group<float, 1, 2 * U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
+    }
+}
+
+template <int WIN>
+int rows_launch(const RowsArgs& A, int items, hipStream_t stream)
+{
+    const int64_t units = (A.n + WIN - 1) / WIN;
+    const dim3 gd((unsigned)((units + kRowsWaves - 1) / kRowsWaves)), bd(kThreads);
+    switch (items) {
+    case 2: hipLaunchKernelGGL((rows_kernel<WIN, 2>), gd, bd, 0, stream, A); break;
+    case 4: hipLaunchKernelGGL((rows_kernel<WIN, 4>), gd, bd, 0, stream, A); break;
+    case 8: hipLaunchKernelGGL((rows_kernel<WIN, 8>), gd, bd, 0, stream, A); break;
+    default: return -1;
+    }
+    return (int)hipGetLastError();
+}
+
 enum Mix { kRmw = 0, kCopy = 1, kRead = 2 };
 
 struct Args {
@@ -200,6 +317,53 @@ extern "C" int gsprobe_read_cfg(const void* src, int64_t n16, float* sink, int w
     if (bad(src) || sink == nullptr || bad_n(n16) || bad_shape(width, items, blocks, nt_load)) return -1;
     return dispatch(kRead, Args{const_cast<void*>(src), sink, nullptr, nullptr, n16, blocks}, width, items, nt_load,
                     0, stream);
+}
+
+// The masked step's access pattern (rows_kernel above).  mask: n bytes
+// (device), t: n counters (device); p, g, m, v: host arrays of n_groups
+// (1 .. 8) device pointers to FP32 arrays of n x dims[k] floats (dims 1 ..
+// 64), 16-byte aligned where dims[k] is a multiple of 4; n in 1 .. 2^31 - 1;
+// window: primitives per wave (32, 64, 128 or 256); items: chunk items in
+// flight per lane (2, 4 or 8; twice that for single floats).  Return 0, -1
+// on a bad argument (nothing launched), else the HIP error of the launch.
+extern "C" int gsprobe_rows_4r3w_cfg(const uint8_t* mask, int32_t* t, float* const* p, const float* const* g,
+                                     float* const* m, float* const* v, const int32_t* dims, int n_groups, int64_t n,
+                                     int window, int items, hipStream_t stream)
+{
+    if (mask == nullptr || t == nullptr || p == nullptr || g == nullptr || m == nullptr || v == nullptr ||
+        dims == nullptr || n_groups < 1 || n_groups > kMaxRowGroups || n < 1 || n > 0x7fffffff ||
+        (items != 2 && items != 4 && items != 8))
+        return -1;
+    RowsArgs A{};
+    A.mask = mask;
+    A.t = t;
+    A.n_groups = n_groups;
+    A.n = n;
+    for (int k = 0; k < n_groups; ++k) {
+        if (dims[k] < 1 || dims[k] > 64 || p[k] == nullptr || g[k] == nullptr || m[k] == nullptr || v[k] == nullptr)
+            return -1;
+        if (dims[k] % 4 == 0 && (bad(p[k]) || bad(g[k]) || bad(m[k]) || bad(v[k]))) return -1;
+        A.p[k] = p[k];
+        A.g[k] = g[k];
+        A.m[k] = m[k];
+        A.v[k] = v[k];
+        A.dim[k] = dims[k];
+    }
+    switch (window) {
+    case 32: return rows_launch<32>(A, items, stream);
+    case 64: return rows_launch<64>(A, items, stream);
+    case 128: return rows_launch<128>(A, items, stream);
+    case 256: return rows_launch<256>(A, items, stream);
+    default: return -1;
+    }
+}
+
+// The shape of the masked step: windows of 32, four chunk items in flight.
+extern "C" int gsprobe_rows_4r3w(const uint8_t* mask, int32_t* t, float* const* p, const float* const* g,
+                                 float* const* m, float* const* v, const int32_t* dims, int n_groups, int64_t n,
+                                 hipStream_t stream)
+{
+    return gsprobe_rows_4r3w_cfg(mask, t, p, g, m, v, dims, n_groups, n, 32, 4, stream);
 }
 
 // The fixed shape the benchmark reports by default: 16-byte accesses, four
