@@ -335,15 +335,15 @@ ROWS_PROBE_SHAPES = [(w, it) for w in (32, 64, 128, 256) for it in (2, 4, 8)]
 
 
 def rows_ceiling(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 50, warmup: int = 5,
-                 shapes=None) -> dict:
+                 shapes=None, moments: str = "f32") -> dict:
     """The masked step's own access pattern with no method arithmetic
     (bench_probe rows_kernel): per step, gs_visibility writes the camera's
     mask (not timed), then the probe reads and writes exactly the rows and
     bytes the masked FP32 step does (the five groups' four arrays, the step
     counters), timed with HIP events, for each launch shape (window of
-    primitives per wave, chunk items in flight per lane) in `shapes`.  Same
-    accounting as the step: BYTES_PER_VISIBLE per visible row plus 1 B of
-    mask per primitive.  The ratio of a step kernel's bandwidth to the best
+    primitives per wave, chunk items in flight per lane) in `shapes`, with
+    FP32 or BF16 moment arrays.  Same accounting as the step:
+    BYTES_PER_VISIBLE per visible row plus 1 B of mask per primitive.  The ratio of a step kernel's bandwidth to the best
     shape's is how close it comes to what its access pattern allows."""
     import ctypes
 
@@ -353,8 +353,10 @@ def rows_ceiling(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 50, war
     dev = torch.device(DEVICE)
     lib = bench_probe.load()
     arrs = []
+    mdt = torch.bfloat16 if moments == "bf16" else torch.float32
     for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads):
-        arrs.append((p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p)))
+        arrs.append((p.clone(), sets[0], torch.zeros(p.shape, dtype=mdt, device=dev),
+                     torch.zeros(p.shape, dtype=mdt, device=dev)))
     t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
     mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
     idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
@@ -378,7 +380,8 @@ def rows_ceiling(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 50, war
             if j >= 0:
                 ev.record("start", j, stream)
             rc = lib.gsprobe_rows_4r3w_cfg(ctypes.c_void_p(mask.data_ptr()), ctypes.c_void_p(t.data_ptr()),
-                                           ptrs[0], ptrs[1], ptrs[2], ptrs[3], dims, ng, N_PRIMS, win, items, sp)
+                                           ptrs[0], ptrs[1], ptrs[2], ptrs[3], dims, ng, N_PRIMS, win, items,
+                                           int(moments == "bf16"), sp)
             if rc != 0:
                 raise RuntimeError(f"gsprobe_rows_4r3w_cfg returned {rc}")
             if j >= 0:
@@ -387,20 +390,21 @@ def rows_ceiling(gs, torch, sd: SceneOnDevice, cams, order, steps: int = 50, war
         durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
         ev.close()
         nv = counts.cpu().numpy().astype(np.int64)[warmup:]
-        byts = nv * BYTES_PER_VISIBLE["f32"] + N_PRIMS * BYTES_PER_PRIMITIVE["two_launch"]
+        byts = nv * BYTES_PER_VISIBLE[moments] + N_PRIMS * BYTES_PER_PRIMITIVE["two_launch"]
         table[f"win{win}_i{items}"] = {"GBps": float(byts.sum() / durs.sum()) / 1e9, "us": float(durs.mean() * 1e6)}
     del arrs, t, mask, idx
     torch.cuda.empty_cache()
     best = max(table, key=lambda k: table[k]["GBps"])
     step_shape = "win32_i4"
-    return {"GBps": table[step_shape]["GBps"] if step_shape in table else None,
+    return {"moments": moments,
+            "GBps": table[step_shape]["GBps"] if step_shape in table else None,
             "us": table[step_shape]["us"] if step_shape in table else None,
             "best_GBps": table[best]["GBps"], "best_shape": best, "table": table,
             "visible_mean": float(nv.mean()), "steps": steps,
             "kind": "masked-step access pattern without arithmetic (bench_probe rows_kernel): the five groups' "
-                    "attribute, gradient and moment arrays and the step counters; GBps: the step's shape "
-                    "(windows of 32, 4 chunk items in flight); best: fastest of windows 32-256 x 2-8 items; "
-                    "1660 B per visible + 1 B of mask per primitive"}
+                    "attribute, gradient and moment arrays and the step counters; GBps: windows of 32, 4 chunk "
+                    "items in flight; best: fastest of windows 32-256 x 2-8 items; "
+                    f"{BYTES_PER_VISIBLE[moments]} B per visible + 1 B of mask per primitive"}
 
 
 def gpu_clocks():
@@ -1064,7 +1068,7 @@ PACKED_COLUMNS = {"sh": 0, "quats": 48, "means": 52, "scales": 55, "opacity": 58
 
 def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
                 forms=("batched_bf16", "batched_bf16_packed", "batched_bf16_resident", "per_scene_bf16",
-                       "per_scene_f32")):
+                       "per_scene_f32"), rows_probe: bool = True):
     """Many-scene workload: 16 scenes with sizes log-uniform in [2e5, 4e6] and
     visible ratios U[0.02, 0.60] (Bernoulli visibility, 8 pre-drawn masks per
     scene used in turn), 59 attributes each.  Times three forms of the same
@@ -1173,9 +1177,66 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
     for form in forms:
         wall = timed(form)
         out[form] = {"value": vis_total * 59 / wall, "ms_per_step": wall / steps * 1e3}
+    if rows_probe:
+        rp = guarded("batched rows probe", batched_rows_ceiling, torch, scenes, n_masks, min(steps, 40))
+        if "error" not in rp:
+            rp["alg_GBps"] = {k: out["algorithmic_bytes_per_step_bf16"] / (v * 1e-3) / 1e9
+                              for k, v in rp["kernel_ms_per_step"].items()}
+        out["rows_probe_bf16"] = rp
     scenes.clear()
     torch.cuda.empty_cache()
     return out
+
+
+def batched_rows_ceiling(torch, scenes, n_masks: int, steps: int,
+                         shapes=((32, 4), (64, 4), (128, 4), (32, 8), (64, 8), (128, 8))) -> dict:
+    """The rows probe (the masked step's access pattern, no arithmetic; BF16
+    moments) over each scene of the batch with its own masks, one launch per
+    scene, each launch timed with HIP events; the sum over the scenes of a
+    step is that step's kernel time.  Per launch shape (window, chunk items
+    in flight), the mean over `steps` steps."""
+    import ctypes
+
+    import bench_probe
+    import synth
+    dev = torch.device(DEVICE)
+    lib = bench_probe.load()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    dims = [d for _, d, _, _ in synth.GROUPS_59]
+    ng = len(dims)
+    cd = (ctypes.c_int32 * ng)(*dims)
+    res = {}
+    for (win, items) in shapes:
+        total_ms = 0.0
+        for sc in scenes:
+            n = sc["n"]
+            arrs = [(p.clone(), g, torch.zeros(p.shape, dtype=torch.bfloat16, device=dev),
+                     torch.zeros(p.shape, dtype=torch.bfloat16, device=dev)) for p, g in zip(sc["params"], sc["grads"])]
+            t = torch.zeros(n, dtype=torch.int32, device=dev)
+            ptrs = [(ctypes.c_void_p * ng)(*[a[k].data_ptr() for a in arrs]) for k in range(4)]
+            ev = TimingEvents(steps)
+            for k in range(steps + 2):
+                j = k - 2
+                if j >= 0:
+                    ev.record("start", j, stream)
+                rc = lib.gsprobe_rows_4r3w_cfg(ctypes.c_void_p(sc["masks"][k % n_masks].data_ptr()),
+                                               ctypes.c_void_p(t.data_ptr()), ptrs[0], ptrs[1], ptrs[2], ptrs[3],
+                                               cd, ng, n, win, items, 1, sp)
+                if rc != 0:
+                    raise RuntimeError(f"gsprobe_rows_4r3w_cfg returned {rc}")
+                if j >= 0:
+                    ev.record("end", j, stream)
+            torch.cuda.synchronize()
+            total_ms += float(np.mean([ev.ms(j) for j in range(steps)]))
+            ev.close()
+            del arrs, t
+        res[f"win{win}_i{items}"] = total_ms
+    torch.cuda.empty_cache()
+    best = min(res, key=res.get)
+    return {"kernel_ms_per_step": res, "best_shape": best, "best_kernel_ms_per_step": res[best],
+            "kind": "rows probe (masked-step access pattern, BF16 moments, no arithmetic) per scene with the "
+                    "scene's own masks; per step: sum of the scenes' kernel times"}
 
 
 def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10, path: str = "two_launch", counts_from=None):
@@ -1350,6 +1411,14 @@ def main(argv=None) -> int:
         two.pop("counts")
         two.pop("state")
         rows = rows_ceiling(gs, torch, sd, cams, order, steps=args.steps, warmup=args.warmup)
+        rows["two_launch_step_GBps"] = two["achieved_GBps"]
+        rows["two_launch_step_us"] = two["step_kernel_us"]
+        rows["two_launch_step_frac_of_best"] = two["achieved_GBps"] / rows["best_GBps"]
+        print(json.dumps(rows), flush=True)
+        two = run_steps(gs, torch, sd, cams, order, "bf16", args.steps, args.warmup)
+        two.pop("counts")
+        two.pop("state")
+        rows = rows_ceiling(gs, torch, sd, cams, order, steps=args.steps, warmup=args.warmup, moments="bf16")
         rows["two_launch_step_GBps"] = two["achieved_GBps"]
         rows["two_launch_step_us"] = two["step_kernel_us"]
         rows["two_launch_step_frac_of_best"] = two["achieved_GBps"] / rows["best_GBps"]
@@ -1563,13 +1632,18 @@ def main(argv=None) -> int:
         ceil["kind"] = ("plain contiguous kernels over 4 x 1 GiB arrays (bench_probe); *_GBps: 16-byte "
                         "non-temporal accesses, 4 in flight per thread, one tile per block; *_best_GBps: the "
                         "fastest of the swept launch shapes (width, in flight, hints, grid form)")
-    if args.moments == "f32":
-        rows = guarded("rows probe", rows_ceiling, gs, torch, layouts_head, cams, order)
+    # the rows probe in both moment precisions, beside the step lines of the
+    # same order and precision
+    for mo in ("f32", "bf16"):
+        rows = guarded(f"rows probe ({mo} moments)", rows_ceiling, gs, torch, layouts_head, cams, order,
+                       moments=mo)
         if "error" not in rows:
-            rows["two_launch_step_frac_of_best"] = two_frac_src["achieved_GBps"] / rows["best_GBps"]
-            rows["fused_step_frac_of_best"] = head["achieved_GBps"] / rows["best_GBps"]
+            for line in [dict(head, path=args.path, moments=args.moments, order=args.order)] + \
+                    [v for v in variants if isinstance(v, dict) and "achieved_GBps" in v]:
+                if line.get("moments") == mo and line.get("order") == args.order:
+                    rows[f"{line['path']}_step_frac_of_best"] = line["achieved_GBps"] / rows["best_GBps"]
         if isinstance(ceil, dict):
-            ceil["rows"] = rows
+            ceil[f"rows_{mo}"] = rows
     out["stream_ceiling"] = ceil
     out["gpu_clocks"] = gpu_clocks()
     if not args.no_cpu_baseline:

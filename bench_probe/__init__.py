@@ -40,5 +40,5 @@ def load():
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.gsprobe_rows_4r3w.argtypes = [vp, vp, pp, pp, pp, pp, ctypes.POINTER(ctypes.c_int32), i32, i64, vp]
     lib.gsprobe_rows_4r3w_cfg.argtypes = [vp, vp, pp, pp, pp, pp, ctypes.POINTER(ctypes.c_int32), i32, i64, i32, i32,
-                                          vp]
+                                          i32, vp]
     return lib

@@ -125,24 +125,42 @@ struct RowsArgs {
     int32_t* t;
     float* p[kMaxRowGroups];
     const float* g[kMaxRowGroups];
-    float* m[kMaxRowGroups];
-    float* v[kMaxRowGroups];
+    void* m[kMaxRowGroups];
+    void* v[kMaxRowGroups];
     int32_t dim[kMaxRowGroups];
     int32_t n_groups;
     int64_t n;
 };
 
-template <typename T, int V, int U>
-__device__ __forceinline__ void rows_group(float* P, const float* G, float* M, float* W, int dim, const int* rows,
+typedef uint32_t u2x32 __attribute__((ext_vector_type(2)));
+
+// The values written back: blends of the ones read for FP32 moments; for
+// BF16 moments (4 packed in 8 bytes, or 1 in 2 bytes) the bits read with
+// each element's lowest bit flipped.
+__device__ __forceinline__ f4 mix_m(f4 x, f4 b) { return 0.875f * x + 0.125f * b; }
+__device__ __forceinline__ float mix_m(float x, float b) { return 0.875f * x + 0.125f * b; }
+__device__ __forceinline__ f4 mix_v(f4 y, f4 b) { return 0.5f * y + 0.5f * b * b; }
+__device__ __forceinline__ float mix_v(float y, float b) { return 0.5f * y + 0.5f * b * b; }
+__device__ __forceinline__ u2x32 mix_m(u2x32 x, f4) { return x ^ 0x00010001u; }
+__device__ __forceinline__ uint16_t mix_m(uint16_t x, float) { return (uint16_t)(x ^ 1u); }
+__device__ __forceinline__ u2x32 mix_v(u2x32 y, f4) { return y ^ 0x00010001u; }
+__device__ __forceinline__ uint16_t mix_v(uint16_t y, float) { return (uint16_t)(y ^ 1u); }
+
+// T: an attribute chunk (V floats); MT: the moments of a chunk.  Accesses of
+// 8 bytes and more carry the non-temporal hint.
+template <typename T, typename MT, int V, int U>
+__device__ __forceinline__ void rows_group(float* P, const float* G, void* M, void* W, int dim, const int* rows,
                                            int nrows, int lane)
 {
-    constexpr bool NT = V == 4;
+    constexpr bool NT = sizeof(T) >= 8;
+    constexpr bool NTM = sizeof(MT) >= 8;
     const int cpr = dim / V;
     const int items = nrows * cpr;
     int r = lane / cpr, c = lane - (lane / cpr) * cpr;
     const int dr = 64 / cpr, dc = 64 - (64 / cpr) * cpr;
     for (int k0 = lane; k0 < items; k0 += U * 64) {
-        T a[U], b[U], x[U], y[U];
+        T a[U], b[U];
+        MT x[U], y[U];
         int64_t e[U];
         bool ok[U];
 #pragma unroll
@@ -152,8 +170,8 @@ __device__ __forceinline__ void rows_group(float* P, const float* G, float* M, f
             if (ok[u]) {
                 a[u] = ld<NT>(reinterpret_cast<const T*>(P) + e[u]);
                 b[u] = ld<NT>(reinterpret_cast<const T*>(G) + e[u]);
-                x[u] = ld<NT>(reinterpret_cast<const T*>(M) + e[u]);
-                y[u] = ld<NT>(reinterpret_cast<const T*>(W) + e[u]);
+                x[u] = ld<NTM>(static_cast<const MT*>(M) + e[u]);
+                y[u] = ld<NTM>(static_cast<const MT*>(W) + e[u]);
             }
             r += dr;
             c += dc;
@@ -165,15 +183,14 @@ __device__ __forceinline__ void rows_group(float* P, const float* G, float* M, f
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
-            const T mm = 0.875f * x[u] + 0.125f * b[u];
-            st<NT>(a[u] - 0.0625f * mm, reinterpret_cast<T*>(P) + e[u]);
-            st<NT>(mm, reinterpret_cast<T*>(M) + e[u]);
-            st<NT>(0.5f * y[u] + 0.5f * b[u] * b[u], reinterpret_cast<T*>(W) + e[u]);
+            st<NT>(a[u] - 0.0625f * b[u], reinterpret_cast<T*>(P) + e[u]);
+            st<NTM>(mix_m(x[u], b[u]), static_cast<MT*>(M) + e[u]);
+            st<NTM>(mix_v(y[u], b[u]), static_cast<MT*>(W) + e[u]);
         }
     }
 }
 
-template <int WIN, int U>
+template <int WIN, int U, bool BF16>
 __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs A)
 {
     constexpr int R = (WIN + 63) / 64;
@@ -201,25 +218,46 @@ __global__ __launch_bounds__(kThreads) void rows_kernel(RowsArgs A)
         A.t[row] = A.t[row] + 1;
     }
     for (int gi = 0; gi < A.n_groups; ++gi) {
-        if (A.dim[gi] % 4 == 0)
-            rows_group<f4, 4, U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
-        else
-            rows_group<float, 1, 2 * U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
+        if (A.dim[gi] % 4 == 0) {
+            if constexpr (BF16)
+                rows_group<f4, u2x32, 4, U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
+            else
+                rows_group<f4, f4, 4, U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave], nrows, lane);
+        } else {
+            if constexpr (BF16)
+                rows_group<float, uint16_t, 1, 2 * U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave],
+                                                      nrows, lane);
+            else
+                rows_group<float, float, 1, 2 * U>(A.p[gi], A.g[gi], A.m[gi], A.v[gi], A.dim[gi], s_row[wave],
+                                                   nrows, lane);
+        }
     }
 }
 
-template <int WIN>
+template <int WIN, bool BF16>
 int rows_launch(const RowsArgs& A, int items, hipStream_t stream)
 {
     const int64_t units = (A.n + WIN - 1) / WIN;
     const dim3 gd((unsigned)((units + kRowsWaves - 1) / kRowsWaves)), bd(kThreads);
     switch (items) {
-    case 2: hipLaunchKernelGGL((rows_kernel<WIN, 2>), gd, bd, 0, stream, A); break;
-    case 4: hipLaunchKernelGGL((rows_kernel<WIN, 4>), gd, bd, 0, stream, A); break;
-    case 8: hipLaunchKernelGGL((rows_kernel<WIN, 8>), gd, bd, 0, stream, A); break;
+    case 2: hipLaunchKernelGGL((rows_kernel<WIN, 2, BF16>), gd, bd, 0, stream, A); break;
+    case 4: hipLaunchKernelGGL((rows_kernel<WIN, 4, BF16>), gd, bd, 0, stream, A); break;
+    case 8: hipLaunchKernelGGL((rows_kernel<WIN, 8, BF16>), gd, bd, 0, stream, A); break;
     default: return -1;
     }
     return (int)hipGetLastError();
+}
+
+template <bool BF16>
+int rows_by_window(const RowsArgs& A, int window, int items, hipStream_t stream)
+{
+    switch (window) {
+    case 32: return rows_launch<32, BF16>(A, items, stream);
+    case 64: return rows_launch<64, BF16>(A, items, stream);
+    case 128: return rows_launch<128, BF16>(A, items, stream);
+    case 256: return rows_launch<256, BF16>(A, items, stream);
+    default: return -1;
+    }
 }
 
 enum Mix { kRmw = 0, kCopy = 1, kRead = 2 };
@@ -321,19 +359,23 @@ extern "C" int gsprobe_read_cfg(const void* src, int64_t n16, float* sink, int w
 
 // The masked step's access pattern (rows_kernel above).  mask: n bytes
 // (device), t: n counters (device); p, g, m, v: host arrays of n_groups
-// (1 .. 8) device pointers to FP32 arrays of n x dims[k] floats (dims 1 ..
-// 64), 16-byte aligned where dims[k] is a multiple of 4; n in 1 .. 2^31 - 1;
-// window: primitives per wave (32, 64, 128 or 256); items: chunk items in
-// flight per lane (2, 4 or 8; twice that for single floats).  Return 0, -1
-// on a bad argument (nothing launched), else the HIP error of the launch.
+// (1 .. 8) device pointers to arrays of n x dims[k] elements (dims 1 .. 64):
+// FP32 attributes and gradients, moments in FP32 (bf16 = 0) or BF16 (1);
+// where dims[k] is a multiple of 4, the attribute and gradient arrays are
+// 16-byte aligned and the moment arrays 16-byte (FP32) or 8-byte (BF16)
+// aligned; n in 1 .. 2^31 - 1; window: primitives per wave (32, 64, 128 or
+// 256); items: chunk items in flight per lane (2, 4 or 8; twice that for
+// single elements).  Return 0, -1 on a bad argument (nothing launched), else
+// the HIP error of the launch.
 extern "C" int gsprobe_rows_4r3w_cfg(const uint8_t* mask, int32_t* t, float* const* p, const float* const* g,
-                                     float* const* m, float* const* v, const int32_t* dims, int n_groups, int64_t n,
-                                     int window, int items, hipStream_t stream)
+                                     void* const* m, void* const* v, const int32_t* dims, int n_groups, int64_t n,
+                                     int window, int items, int bf16, hipStream_t stream)
 {
     if (mask == nullptr || t == nullptr || p == nullptr || g == nullptr || m == nullptr || v == nullptr ||
         dims == nullptr || n_groups < 1 || n_groups > kMaxRowGroups || n < 1 || n > 0x7fffffff ||
-        (items != 2 && items != 4 && items != 8))
+        (items != 2 && items != 4 && items != 8) || (bf16 != 0 && bf16 != 1))
         return -1;
+    const uintptr_t malign = bf16 ? 8 : 16;
     RowsArgs A{};
     A.mask = mask;
     A.t = t;
@@ -342,28 +384,24 @@ extern "C" int gsprobe_rows_4r3w_cfg(const uint8_t* mask, int32_t* t, float* con
     for (int k = 0; k < n_groups; ++k) {
         if (dims[k] < 1 || dims[k] > 64 || p[k] == nullptr || g[k] == nullptr || m[k] == nullptr || v[k] == nullptr)
             return -1;
-        if (dims[k] % 4 == 0 && (bad(p[k]) || bad(g[k]) || bad(m[k]) || bad(v[k]))) return -1;
+        if (dims[k] % 4 == 0 && (bad(p[k]) || bad(g[k]) || (uintptr_t)m[k] % malign != 0 ||
+                                 (uintptr_t)v[k] % malign != 0))
+            return -1;
         A.p[k] = p[k];
         A.g[k] = g[k];
         A.m[k] = m[k];
         A.v[k] = v[k];
         A.dim[k] = dims[k];
     }
-    switch (window) {
-    case 32: return rows_launch<32>(A, items, stream);
-    case 64: return rows_launch<64>(A, items, stream);
-    case 128: return rows_launch<128>(A, items, stream);
-    case 256: return rows_launch<256>(A, items, stream);
-    default: return -1;
-    }
+    return bf16 ? rows_by_window<true>(A, window, items, stream) : rows_by_window<false>(A, window, items, stream);
 }
 
-// The shape of the masked step: windows of 32, four chunk items in flight.
+// The shape of the masked FP32 step: windows of 32, four chunk items in flight.
 extern "C" int gsprobe_rows_4r3w(const uint8_t* mask, int32_t* t, float* const* p, const float* const* g,
-                                 float* const* m, float* const* v, const int32_t* dims, int n_groups, int64_t n,
+                                 void* const* m, void* const* v, const int32_t* dims, int n_groups, int64_t n,
                                  hipStream_t stream)
 {
-    return gsprobe_rows_4r3w_cfg(mask, t, p, g, m, v, dims, n_groups, n, 32, 4, stream);
+    return gsprobe_rows_4r3w_cfg(mask, t, p, g, m, v, dims, n_groups, n, 32, 4, 0, stream);
 }
 
 // The fixed shape the benchmark reports by default: 16-byte accesses, four

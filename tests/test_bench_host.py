@@ -259,6 +259,9 @@ def test_default_run_under_the_driver_flags_prints_its_line(monkeypatch, capsys)
     monkeypatch.setattr(bench, "TimingEvents", _FakeEvents)
     monkeypatch.setattr(bench, "stream_ceilings",
                         lambda torch: {"rmw_4r3w_GBps": 5000.0, "rmw_4r3w_best_GBps": 6000.0, "table": {}})
+    # the probes' kernels need a GPU: their results are stood in for
+    monkeypatch.setattr(bench, "rows_ceiling", lambda *a, **k: {"GBps": 5500.0, "best_GBps": 5600.0})
+    monkeypatch.setattr(bench, "batched_rows_ceiling", lambda *a, **k: {"kernel_ms_per_step": {"win32_i4": 2.0}})
     stream = types.SimpleNamespace(cuda_stream=0)
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
     monkeypatch.setattr(torch.cuda, "empty_cache", lambda *a: None)
@@ -290,6 +293,8 @@ def test_default_run_under_the_driver_flags_prints_its_line(monkeypatch, capsys)
     for v in out["variants"]:
         names.update(v.keys())
     assert {"next_rows", "unfused_comparator", "config1_100k", "batched", "mcmc_6m"} <= names
+    assert {"rows_f32", "rows_bf16"} <= set(out["stream_ceiling"])
+    assert "two_launch_step_frac_of_best" in out["stream_ceiling"]["rows_f32"]
     assert fake.calls["step_view"] > 200 and fake.calls["relocate"] > 0 and fake.calls["batched"] > 0
 
 

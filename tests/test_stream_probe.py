@@ -92,3 +92,82 @@ def test_every_swept_launch_shape_does_its_work():
                                    err_msg=str(shape))
         np.testing.assert_array_equal(dst.cpu().numpy(), G, err_msg=str(shape))
     assert sink.cpu().numpy()[0] == 0.0
+
+
+def _rows_args(arrs):
+    ng = len(arrs)
+    ptrs = [(ctypes.c_void_p * ng)(*[a[k] for a in arrs]) for k in range(4)]
+    return ptrs
+
+
+def test_rows_probe_rejects_bad_arguments_before_any_launch():
+    lib = _lib()
+    dims = (ctypes.c_int32 * 2)(3, 48)
+    good = [(16, 32, 48, 64), (80, 96, 112, 128)]
+    ptrs = _rows_args(good)
+    assert lib.gsprobe_rows_4r3w_cfg(None, 16, *ptrs, dims, 2, 100, 32, 4, 0, None) == -1      # mask
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 0, 100, 32, 4, 0, None) == -1        # no group
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 9, 100, 32, 4, 0, None) == -1        # too many
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 2, 0, 32, 4, 0, None) == -1          # empty
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 2, 100, 48, 4, 0, None) == -1        # window
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 2, 100, 32, 3, 0, None) == -1        # items
+    bad_dims = (ctypes.c_int32 * 2)(3, 65)
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, bad_dims, 2, 100, 32, 4, 0, None) == -1    # width
+    mis = _rows_args([(16, 32, 48, 64), (80, 100, 112, 128)])                               # 4-wide, misaligned
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *mis, dims, 2, 100, 32, 4, 0, None) == -1
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *ptrs, dims, 2, 100, 32, 4, 2, None) == -1     # moment type
+    mis8 = _rows_args([(16, 32, 48, 64), (80, 96, 116, 128)])                               # BF16 moments at 4 B
+    assert lib.gsprobe_rows_4r3w_cfg(16, 16, *mis8, dims, 2, 100, 32, 4, 1, None) == -1
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bf16", [0, 1])
+def test_rows_probe_touches_exactly_the_masked_rows_in_every_shape(bf16):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import bench
+    lib = _lib()
+    dev = torch.device("cuda:0")
+    n = 4 * 256 + 77                          # several windows of every size and a ragged tail
+    dims = [3, 3, 4, 1, 48]
+    r = np.random.default_rng(8)
+    mask_h = (r.random(n) < 0.35).astype(np.uint8)
+    mask_h[:64] = 1                           # a full window
+    mask_h[64:128] = 0                        # an empty one
+    keep = mask_h.astype(bool)
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for (win, items) in bench.ROWS_PROBE_SHAPES:
+        host = []
+        for d in dims:
+            p, g = (r.standard_normal((n, d)).astype(np.float32) for _ in range(2))
+            if bf16:
+                m, v = (r.integers(0, 1 << 16, (n, d)).astype(np.uint16) for _ in range(2))
+            else:
+                m, v = (r.standard_normal((n, d)).astype(np.float32) for _ in range(2))
+            host.append((p, g, m, v))
+        dev_arrs = [[torch.from_numpy(h.view(np.int16) if h.dtype == np.uint16 else h).to(dev) for h in grp]
+                    for grp in host]
+        t = torch.zeros(n, dtype=torch.int32, device=dev)
+        mask = torch.from_numpy(mask_h).to(dev)
+        ptrs = [(ctypes.c_void_p * len(dims))(*[grp[k].data_ptr() for grp in dev_arrs]) for k in range(4)]
+        cd = (ctypes.c_int32 * len(dims))(*dims)
+        assert lib.gsprobe_rows_4r3w_cfg(mask.data_ptr(), t.data_ptr(), *ptrs, cd, len(dims), n, win, items, bf16,
+                                         sp) == 0
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(t.cpu().numpy(), keep.astype(np.int32))
+        for (P, G, M, V), grp in zip(host, dev_arrs):
+            pp = P - np.float32(0.0625) * G
+            np.testing.assert_allclose(grp[0].cpu().numpy(), np.where(keep[:, None], pp, P), rtol=1e-6, atol=1e-7,
+                                       err_msg=f"window {win}, items {items}")
+            np.testing.assert_array_equal(grp[1].cpu().numpy(), G)
+            if bf16:
+                for want, got in ((M, grp[2]), (V, grp[3])):
+                    np.testing.assert_array_equal(got.cpu().numpy().view(np.uint16),
+                                                  np.where(keep[:, None], want ^ np.uint16(1), want))
+            else:
+                mm = np.float32(0.875) * M + np.float32(0.125) * G
+                vv = np.float32(0.5) * V + np.float32(0.5) * G * G
+                for want, got in ((np.where(keep[:, None], mm, M), grp[2]), (np.where(keep[:, None], vv, V), grp[3])):
+                    np.testing.assert_allclose(got.cpu().numpy(), want, rtol=1e-6, atol=1e-7,
+                                               err_msg=f"window {win}, items {items}")
