@@ -125,10 +125,14 @@ class TimingEvents:
 
 
 def kernel_source_hash(path: str = "view") -> str:
+    """Hash of the kernel's sources and of the library's build script (its
+    compiler flags shape the machine code too)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[path]:
         with open(os.path.join(ROOT, "paper_2601_16736_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2601_16736_amd", "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -988,10 +992,14 @@ def run_profile_set(gs, torch, reps: int = 10) -> dict:
     --pmc): on the 3M scene (means U[-10, 10]^3 drawn on the device, Morton
     order, other attributes N(0, 1), z_far 17.5) `reps` fused view steps with
     FP32 moments, `reps` with BF16 moments, `reps` / 2 dense steps (every
-    primitive visible, windows of 64) with FP32 moments; then the streaming
-    probes' 4-read / 3-write mix in its default and best swept shapes and the
-    copy in its best shape, `reps` launches each over 4 x 1 GiB.  Each
-    kernel is told apart by its name (template arguments) in the trace."""
+    primitive visible, windows of 64) with FP32 moments, `reps` two-launch
+    steps (visibility, then the masked step in windows of 32) with FP32
+    moments; the rows probe on the same cameras' masks (FP32 moments in the
+    step's shape and in 8 items in flight, BF16 in the step's shape), `reps`
+    each; then the streaming probes' 4-read / 3-write mix in its default and
+    best swept shapes and the copy in its best shape, `reps` launches each
+    over 4 x 1 GiB.  Each kernel is told apart by its name (template
+    arguments) in the trace."""
     import ctypes
 
     import bench_probe
@@ -1013,9 +1021,13 @@ def run_profile_set(gs, torch, reps: int = 10) -> dict:
     order = synth.camera_order(len(cams), 4 * reps, seed=1)
     stream = torch.cuda.current_stream()
     out = {}
+    mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
     for label, mdt, mom, sched, count in (("view_f32", torch.float32, GS_F32, None, reps),
                                           ("view_bf16", torch.bfloat16, GS_BF16, None, reps),
-                                          ("dense_f32", torch.float32, GS_F32, 3, max(reps // 2, 1))):
+                                          ("dense_f32", torch.float32, GS_F32, 3, max(reps // 2, 1)),
+                                          ("masked_f32", torch.float32, GS_F32, 2, reps)):
         groups = [gs.Group(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev),
                            torch.zeros(p.shape, dtype=mdt, device=dev), lr, dar_kind=dar,
                            dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
@@ -1027,18 +1039,40 @@ def run_profile_set(gs, torch, reps: int = 10) -> dict:
             if sched is None:
                 gs.adamw_gs_step_view(groups, n, t, cfg, groups[0].param, gcams[order[k % len(order)]],
                                       stream=stream)
+            elif sched == 2:
+                gs.gs_visibility(groups[0].param, gcams[order[k % len(order)]], mask=mask, vis_idx=idx,
+                                 vis_count=cnt, stream=stream)
+                cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k + 1, moment_dtype=mom, **STEP_LAUNCH)
+                gs.adamw_gs_step(groups, n, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
             else:
                 gs.adamw_gs_step(groups, n, t, cfg, stream=stream)
         torch.cuda.synchronize()
         out[label] = count
         del groups, t
-    del params, grads, means
-    torch.cuda.empty_cache()
     lib = bench_probe.load()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    dims = (ctypes.c_int32 * len(params))(*[p.shape[1] for p in params])
+    for label, mdt, bf16, win, items in (("rows_f32", torch.float32, 0, 32, 4), ("rows_f32_i8", torch.float32, 0, 32, 8),
+                                         ("rows_bf16", torch.bfloat16, 1, 32, 4)):
+        arrs = [(p.clone(), g, torch.zeros(p.shape, dtype=mdt, device=dev), torch.zeros(p.shape, dtype=mdt, device=dev))
+                for p, g in zip(params, grads)]
+        ptrs = [(ctypes.c_void_p * len(arrs))(*[a[j].data_ptr() for a in arrs]) for j in range(4)]
+        t = torch.zeros(n, dtype=torch.int32, device=dev)
+        for k in range(reps):
+            gs.gs_visibility(params[0], gcams[order[k % len(order)]], mask=mask, vis_idx=idx, vis_count=cnt,
+                             stream=stream)
+            rc = lib.gsprobe_rows_4r3w_cfg(ctypes.c_void_p(mask.data_ptr()), ctypes.c_void_p(t.data_ptr()), ptrs[0],
+                                           ptrs[1], ptrs[2], ptrs[3], dims, len(arrs), n, win, items, bf16, sp)
+            if rc != 0:
+                raise RuntimeError(f"gsprobe_rows_4r3w_cfg returned {rc}")
+        torch.cuda.synchronize()
+        out[label] = reps
+        del arrs, t
+    del params, grads, means, mask, idx, cnt
+    torch.cuda.empty_cache()
     nbytes = 1 << 30
     arrs = [torch.rand(nbytes // 4, device=dev) for _ in range(4)]
     ptr = [a.data_ptr() for a in arrs]
-    sp = ctypes.c_void_p(stream.cuda_stream)
     for (w, it, ntl, nts) in ((16, 4, 1, 1), (8, 2, 1, 1)):
         for _ in range(reps):
             lib.gsprobe_rmw_4r3w_cfg(ptr[0], ptr[1], ptr[2], ptr[3], nbytes // 16, w, it, ntl, nts, 0, sp)

@@ -46,7 +46,8 @@ def test_traffic_lookup_only_for_the_measured_source_and_layout(tmp_path, monkey
 def test_committed_traffic_summaries_name_the_sources_they_cover():
     for path in ("view", "two_launch"):
         d = json.load(open(bench.TRAFFIC_FILES[path]))
-        assert d["hash_covers"] == list(bench.KERNEL_SOURCES[path])
+        assert d["hash_covers"] == list(bench.KERNEL_SOURCES[path]) + ["build.py"]
+        assert d["source_hash"] == bench.kernel_source_hash(path), "counters taken on other sources or flags"
         assert d["bytes_per_launch"] == pytest.approx(d["fetched"] + d["written"])
 
 
