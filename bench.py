@@ -74,6 +74,7 @@ GS_F32, GS_BF16 = 0, 1               # moment dtypes (gs_moment_dtype)
 # primitives per wave window in the fused view step: 0 = the library's
 # default, 32 on plain steps and 64 on Re-State iterations
 VIEW_UNIT = 0
+STATE_WARMUP_STEPS = 20                 # discarded steps on a leg's own buffers before its warm-up (state reset after)
 # HBM counter summaries per path, and the sources of the kernel each covers
 TRAFFIC_FILES = {"view": os.path.join(ROOT, "profiles", "step_view_kernel_3M_traffic.json"),
                  "two_launch": os.path.join(ROOT, "profiles", "step_kernel_3M_traffic.json")}
@@ -502,7 +503,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
     gcams = [gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far) for c in cams]
     means = groups[0].param
     stream = torch.cuda.current_stream()
-    ev = TimingEvents(steps)
+    ev = TimingEvents(1 if path == "view" else steps)
     mom = gs.GS_MOMENT_BF16 if moments == "bf16" else gs.GS_MOMENT_F32
 
     def one_step(k: int, slot: int = -1):
@@ -536,20 +537,66 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
             raise ValueError("the fused path needs the visible counts of a two-launch run")
         one_step = one_view_step  # noqa: F811
 
+    region = path == "view"
+    if region:
+        # each timed step's arguments are packed on the host first, before
+        # the warm-up (adamw_gs_step_view marshals tens of microseconds of
+        # Python per call; in a loop that runs ahead of the device this
+        # overlaps the previous step, but the first call after the timer's
+        # synchronization would leave the device idle that long, and packing
+        # them all between the warm-up and the timer would idle it longer
+        # still, letting its clocks fall)
+        launches = []
+        for j in range(steps):
+            k = warmup + j
+            for G, sets in zip(groups, sd.grads):
+                G.grad = sets[k % N_GRAD_SETS]
+            cfg = gs.StepConfig(reg_norm=REG_NORM, seed=0, iteration=k, rsr_enable=(k % RSR_EVERY == 0),
+                                rsr_ratio=RSR_P, rsr_alpha1=RSR_A1, rsr_alpha2=RSR_A2, moment_dtype=mom,
+                                stochastic_round=True, unit=VIEW_UNIT)
+            launches.append(gs.prepare_step_view(groups, N_PRIMS, t, cfg, means, gcams[order[k % len(order)]],
+                                                 stream=stream))
+    # The leg's own buffers first take STATE_WARMUP_STEPS discarded steps
+    # (device clocks fall while the host sets the leg up, and take about 20
+    # steps to come back), then the state is reset by copies: the warm-up and
+    # timed steps below start from exactly the state they would without it.
+    for k in range(STATE_WARMUP_STEPS):
+        one_step(k % total)
+    for G, p in zip(groups, sd.params):
+        G.param.copy_(p)
+        G.exp_avg.zero_()
+        G.exp_avg_sq.zero_()
+    t.zero_()
     for k in range(warmup):
         one_step(k)
     torch.cuda.synchronize()
+    # The fused path launches one kernel per step, so one pair of events
+    # around the timed steps gives its average launch duration: a pair per
+    # step would put an event record between every two launches (about 8 us
+    # of idle each) into the very time being measured.  The two-launch path
+    # brackets its step kernel in every step, apart from the visibility
+    # launches.
     t0 = time.perf_counter()
-    for j in range(steps):
-        one_step(warmup + j, j)
+    if region:
+        ev.record("start", 0, stream)
+        for launch in launches:
+            launch()
+        ev.record("end", 0, stream)
+    else:
+        for j in range(steps):
+            one_step(warmup + j, j)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     all_counts = counts.cpu().numpy().astype(np.int64) if path != "view" else np.asarray(counts_from)
     nv = all_counts[warmup:warmup + steps]
-    durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+    if region:
+        durs = np.full(steps, ev.ms(0) * 1e-3 / steps)
+        plain = np.ones(steps, dtype=bool)      # Re-State steps included (their extra rows not counted)
+    else:
+        durs = np.array([ev.ms(j) for j in range(steps)]) * 1e-3
+        plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
     ev.close()
-    plain = np.array([(warmup + j) % RSR_EVERY != 0 for j in range(steps)])
     step_bytes = nv[plain] * BYTES_PER_VISIBLE[moments] + N_PRIMS * BYTES_PER_PRIMITIVE[path]
     achieved = float(step_bytes.sum() / durs[plain].sum()) / 1e9 if plain.any() else float("nan")
     state = (groups, t) if keep_state else None
@@ -563,7 +610,7 @@ def run_steps(gs, torch, sd: SceneOnDevice, cams, order, moments: str, steps: in
         "achieved_GBps": achieved,
         "step_kernel_us": float(durs[plain].mean() * 1e6) if plain.any() else float("nan"),
         "step_kernel_us_p10_p50_p90": ([float(x) for x in np.percentile(durs[plain] * 1e6, [10, 50, 90])]
-                                       if plain.any() else None),
+                                       if plain.any() and not region else None),
         "counts": all_counts,
     }
 
@@ -1638,6 +1685,7 @@ def main(argv=None) -> int:
                     else STEP_LAUNCH["unit"],
             "same_state_as_two_launch": same_as_two_launch,
             "device_warmup_steps": warm_steps,
+            "state_warmup_steps": STATE_WARMUP_STEPS,
         },
         "roofline": {
             "bound": "hbm",

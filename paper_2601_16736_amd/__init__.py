@@ -179,18 +179,20 @@ def _row_stride(t, dim: int) -> int:
     (dim elements apart).  t is [n][dim] (or [n] for dim 1), possibly a
     column slice of a wider packed tensor; objects without strides (plain
     addresses) count as contiguous."""
-    if t is None or not hasattr(t, "stride") or isinstance(t, int):
+    if t is None or isinstance(t, int):
         return 0
-    if t.shape[0] <= 1 or any(d == 0 for d in t.shape):
-        return 0                        # no second row: the stride is never used
-    if len(t.shape) == 2:
-        if t.shape[1] > 1 and t.stride(1) != 1:
+    try:
+        shape, st = t.shape, t.stride()
+    except AttributeError:
+        return 0
+    if len(shape) == 2:
+        if shape[0] <= 1 or shape[1] == 0:
+            return 0                    # no second row: the stride is never used
+        if shape[1] > 1 and st[1] != 1:
             raise ValueError("attribute rows must have unit element stride")
-        s = int(t.stride(0))
-    elif len(t.shape) == 1:
-        s = int(t.stride(0))
-    else:
+    elif len(shape) != 1 or shape[0] <= 1:
         return 0
+    s = int(st[0])
     return 0 if s == dim else s
 
 
@@ -273,7 +275,8 @@ class Group:
         else read from the tensors, which must then agree."""
         if self.row_stride is not None:
             return int(self.row_stride)
-        found = {_row_stride(t, self.dim) for t in (self.param, self.grad, self.exp_avg, self.exp_avg_sq)
+        dim = self.dim
+        found = {_row_stride(t, dim) for t in (self.param, self.grad, self.exp_avg, self.exp_avg_sq)
                  if t is not None and hasattr(t, "stride")}
         if len(found) > 1:
             raise ValueError(f"param, grad and moments of a group need one row stride, got {sorted(found)}")
@@ -356,12 +359,31 @@ def adamw_gs_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepCon
                        radius=None, visible_out=None, stream=None) -> None:
     """Visibility and step in one launch (see include/gsopt.h).  ``cams`` is a
     Camera or a sequence of up to 32 (their union decides V)."""
+    prepare_step_view(groups, n, step_count, cfg, means, cams, radius, visible_out, stream)()
+
+
+def prepare_step_view(groups: Sequence[Group], n: int, step_count, cfg: StepConfig, means, cams,
+                      radius=None, visible_out=None, stream=None):
+    """The arguments of one adamw_gs_step_view call, marshalled now: returns a
+    function without arguments that makes that call.  The host-side packing
+    (tens of microseconds per call) can then be done ahead of time, e.g.
+    for a loop whose launches should follow one another without host gaps.
+    The returned function keeps the argument objects alive; the tensors'
+    addresses, shapes and the groups' fields are read here, so changing them
+    afterwards does not affect the prepared call."""
     cams = [cams] if isinstance(cams, Camera) else list(cams)
     arr = _groups_c(groups)
     c = cfg.to_c()
     cc = (gs_camera * max(len(cams), 1))(*[x.to_c() for x in cams])
-    _check(_lib.adamw_gs_step_view(arr, len(groups), int(n), _ptr(means), _row_stride(means, 3), _ptr(radius), cc,
-                                   len(cams), _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream)))
+    args = (arr, len(groups), int(n), _ptr(means), _row_stride(means, 3), _ptr(radius), cc, len(cams),
+            _ptr(visible_out), _ptr(step_count), ctypes.byref(c), _stream(stream))
+    keep = (list(groups), [G.grad for G in groups], step_count, means, radius, visible_out, c)
+
+    def launch() -> None:
+        _check(_lib.adamw_gs_step_view(*args))
+
+    launch.keep = keep          # the argument objects live as long as the call
+    return launch
 
 
 # --------------------------------------------------------------------------

@@ -353,3 +353,33 @@ def test_row_strides_are_validated():
         g.to_c()
     assert gs.Group(Strided(FAKE, (10, 3), (64, 1)), Strided(FAKE + 4096, (10, 3), (64, 1)), FAKE + 8192,
                     FAKE + 12288, 1e-3).to_c().row_stride == 64
+
+
+def test_prepared_view_step_makes_the_same_call(monkeypatch):
+    """prepare_step_view packs the arguments at once and its launch passes
+    exactly what adamw_gs_step_view passes; a group changed after the
+    packing does not change the prepared call.  The library entry point is
+    replaced by a recorder, so nothing is launched."""
+    calls = []
+
+    class _Rec:
+        def adamw_gs_step_view(self, *args):
+            calls.append([bytes(a._obj) if type(a).__name__ == "CArgObject" else
+                          (bytes(a) if isinstance(a, ctypes.Array) else a) for a in args])
+            return gs.GS_OK
+
+    monkeypatch.setattr(gs, "_lib", _Rec())
+    cam = gs.Camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 15], 866.0, 866.0, 500, 500, 1000, 1000)
+    groups = [_group(param=_Fake(FAKE, (10, 3)), grad=_Fake(FAKE + 4096, (10, 3))),
+              _group(param=_Fake(FAKE + 65536, (10, 48)), grad=_Fake(FAKE + 69632, (10, 48)), dar_kind=1,
+                     dar_lambda=0.01, dar_clip=2.0)]
+    cfg = gs.StepConfig(iteration=7, rsr_enable=True, rsr_ratio=0.1, unit=64)
+    launch = gs.prepare_step_view(groups, 10, FAKE + 1 << 20, cfg, _Fake(FAKE, (10, 3)), cam, stream=3)
+    gs.adamw_gs_step_view(groups, 10, FAKE + 1 << 20, cfg, _Fake(FAKE, (10, 3)), cam, stream=3)
+    launch()
+    assert calls[0] == calls[1]
+    groups[1].grad = _Fake(FAKE + 131072, (10, 48))
+    launch()
+    assert calls[2] == calls[0]
+    gs.adamw_gs_step_view(groups, 10, FAKE + 1 << 20, cfg, _Fake(FAKE, (10, 3)), cam, stream=3)
+    assert calls[3] != calls[0]

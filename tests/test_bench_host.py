@@ -202,6 +202,10 @@ class _FakeGS:
         if visible_out is not None:
             visible_out.copy_(self._mask(n, cams).to(visible_out.dtype))
 
+    def prepare_step_view(self, groups, n, t, cfg, means, cams, visible_out=None, stream=None):
+        groups = list(groups)
+        return lambda: self.adamw_gs_step_view(groups, n, t, cfg, means, cams, visible_out, stream)
+
     def gs_spatial_order_workspace_size(self, n):
         return 16
 
