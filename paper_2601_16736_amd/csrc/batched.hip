@@ -38,7 +38,10 @@ constexpr int kBatchCap = 512;
 constexpr int kInvWindow = 512;
 // items per lane per trip in the step units (four would spill here)
 constexpr int kBatchUnroll = 2;
-constexpr int kBatchMinWindow = 128;   // smallest masked window in a plan
+// A packed scene's pass needs the 4-wave register budget (launch bounds of
+// the PACKED instances); the per-group instances fit in fewer registers.
+constexpr int kBatchMinWindow = 32;         // smallest masked window in a plan
+constexpr int kBatchMinWindowPacked = 128;  // ... for a scene in packed rows
 constexpr int kBatchMinSlice = 64;     // smallest compacted slice in a plan
 
 
@@ -56,7 +59,7 @@ __device__ __forceinline__ void step_unit(const KScene& S, const KHyper& H, int6
 {
     int nrows = 0;
     if (S.sched == kSchedCompacted) {
-        const int cnt = (int)min((int64_t)*S.count, S.n);
+        const int cnt = (int)min((int64_t)*to_global(S.count), S.n);
         const int64_t base = local * S.unit;
         switch (S.unit) {
         case 32: nrows = build_rows_slice<32>(S.idx, cnt, S.n, base, s_row, lane); break;
@@ -111,26 +114,33 @@ __device__ __forceinline__ int scene_of(const int32_t* first, int n_scenes, int6
 }
 
 template <bool BF16, bool NOISE, bool PACKED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void batched_kernel(KBatch B, KHyper H)
+__global__ __launch_bounds__(kBlock, PACKED ? 4 : 1) void batched_kernel(KBatch B, KHyper H)
 {
     __shared__ int s_row[kWavesPerBlock][kBatchCap];
     __shared__ float s_rb1[kWavesPerBlock][kBatchCap];
     __shared__ float s_rsb2[kWavesPerBlock][kBatchCap];
     __shared__ float s_noise[kWavesPerBlock][NOISE ? 3 * kBatchCap : 1];   // position-noise displacements
-    const int wave = threadIdx.x / kWave;
+    // the wave's index, and so its unit and scene, as a value the compiler
+    // knows to be the same on every lane (scalar registers, scalar loads)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int64_t steps = B.step_first[B.n_scenes];
     const int64_t total = steps + (B.inv ? B.inv_first[B.n_scenes] : 0);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    // The scene table is not written during the launch: read as constant
+    // memory, its fields (the same for the whole wave) load as scalars.
+    typedef const __attribute__((address_space(4))) KScene* scene_cptr;
+    const scene_cptr scenes = (scene_cptr)B.scenes;
     for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave; u < total; u += stride) {
         if (u < steps) {
             const int s = scene_of(B.step_first, B.n_scenes, u);
-            step_unit<BF16, NOISE, PACKED>(B.scenes[s], H, u - B.step_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave],
-                                   s_noise[wave], lane);
+            step_unit<BF16, NOISE, PACKED>(*(const KScene*)(scenes + s), H, u - B.step_first[s], s_row[wave],
+                                           s_rb1[wave], s_rsb2[wave], s_noise[wave], lane);
         } else {
             const int64_t v = u - steps;
             const int s = scene_of(B.inv_first, B.n_scenes, v);
-            invisible_unit<BF16>(B.scenes[s], H, v - B.inv_first[s], s_row[wave], s_rb1[wave], s_rsb2[wave], lane);
+            invisible_unit<BF16>(*(const KScene*)(scenes + s), H, v - B.inv_first[s], s_row[wave], s_rb1[wave],
+                                 s_rsb2[wave], lane);
         }
     }
 }
@@ -243,10 +253,10 @@ extern "C" gs_status gs_batch_create(const gs_scene* scenes, int32_t n_scenes, i
             free_batch(b);
             return st;
         }
-        // a wave reads its scene's descriptors from device memory, a fixed
-        // cost per unit that the smallest windows of one-scene launches do
-        // not amortise
-        if (sched == kSchedMasked) unit = std::max(unit, kBatchMinWindow);
+        // a packed scene's pass serves whole rows: its windows measured
+        // fastest at 128 primitives and more, a contiguous scene's at the
+        // tuner's own sizes (down to 32)
+        if (sched == kSchedMasked) unit = std::max(unit, K.pk_stride > 0 ? kBatchMinWindowPacked : kBatchMinWindow);
         if (sched == kSchedCompacted) unit = std::max(unit, kBatchMinSlice);
         K.sched = sched;
         K.unit = unit;

@@ -78,16 +78,24 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
+// Every array the kernels read or write lives in device (global) memory.  A
+// pointer that a kernel reads from memory, as the batched plan reads its
+// scenes' descriptors, is a generic pointer to the compiler, whose accesses
+// it would issue as flat instructions (slower to wait for: they count against
+// the LDS counter too).  The accessors below name the address space.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
 template <typename T, bool NT> __device__ __forceinline__ T ld(const T* p)
 {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
+    if constexpr (NT) return __builtin_nontemporal_load(to_global(p));
+    else return *to_global(p);
 }
 
 template <typename T, bool NT> __device__ __forceinline__ void st(T* p, T x)
 {
-    if constexpr (NT) __builtin_nontemporal_store(x, p);
-    else *p = x;
+    if constexpr (NT) __builtin_nontemporal_store(x, to_global(p));
+    else *to_global(p) = x;
 }
 
 template <int V> __device__ __forceinline__ void load_f(const float* p, float* x)
@@ -247,8 +255,8 @@ __device__ __forceinline__ void noise_row(const NoiseArgs& nz, int64_t i, float 
     sincospif(2.0f * a2, &sn2, &cs2);
     const float g0 = r1 * cs1, g1 = r1 * sn1, g2 = r2 * cs2;
     // rotation of the normalised quaternion (w, x, y, z)
-    const float* qp = nz.q;
-    const float* kp = nz.kappa;
+    const gptr<const float> qp = to_global(nz.q);
+    const gptr<const float> kp = to_global(nz.kappa);
     float w = qp[nz.sq * i], x = qp[nz.sq * i + 1], y = qp[nz.sq * i + 2], z = qp[nz.sq * i + 3];
     const float inv = 1.0f / __fsqrt_rn(w * w + x * x + y * y + z * z);
     w *= inv; x *= inv; y *= inv; z *= inv;
@@ -259,7 +267,7 @@ __device__ __forceinline__ void noise_row(const NoiseArgs& nz, int64_t i, float 
     const float e0 = (R00 * g0 + R10 * g1 + R20 * g2) * expf(2.0f * kp[nz.sk * i]);
     const float e1 = (R01 * g0 + R11 * g1 + R21 * g2) * expf(2.0f * kp[nz.sk * i + 1]);
     const float e2 = (R02 * g0 + R12 * g1 + R22 * g2) * expf(2.0f * kp[nz.sk * i + 2]);
-    const float o = 1.0f / (1.0f + expf(-nz.tau[nz.st * i]));
+    const float o = 1.0f / (1.0f + expf(-to_global(nz.tau)[nz.st * i]));
     const float gate = 1.0f / (1.0f + expf(k * (o - t0)));            // sigma(-k (o - t))
     out[0] = nz.scale * gate * (R00 * e0 + R01 * e1 + R02 * e2);
     out[1] = nz.scale * gate * (R10 * e0 + R11 * e1 + R12 * e2);
@@ -420,7 +428,7 @@ __device__ __forceinline__ int build_rows_window(const uint8_t* mask, int64_t n,
     for (int b = 0; b < R; ++b) {
         const int64_t i = w0 + b * kWave + lane;
         vis[b] = b * kWave + lane < UNIT && i < n;
-        if (mask != nullptr && vis[b]) vis[b] = mask[i] != 0;
+        if (mask != nullptr && vis[b]) vis[b] = to_global(mask)[i] != 0;
     }
     int nrows = 0;
 #pragma unroll
@@ -452,10 +460,10 @@ __device__ __forceinline__ int build_rows_invisible(const uint8_t* mask, int64_t
 #pragma unroll
     for (int b = 0; b < UNIT / kWave; ++b) {
         const int64_t i = w0 + b * kWave + lane;
-        const bool inv = i < n && mask[i] == 0;
+        const bool inv = i < n && to_global(mask)[i] == 0;
         const bool rsr = inv && H.rsr_thr != 0 && rsr_sampled(rsr_s2, H.rsr_thr, i);
         int ti = 0;
-        if (inv && H.aiu_thr != 0 && rsr_sampled(aiu_s2, H.aiu_thr, i)) ti = t[i];
+        if (inv && H.aiu_thr != 0 && rsr_sampled(aiu_s2, H.aiu_thr, i)) ti = to_global(t)[i];
         const bool aiu = ti > 0;
         const bool pick = rsr || aiu;
         const uint64_t bal = __ballot(pick);
@@ -490,7 +498,7 @@ __device__ __forceinline__ int build_rows_slice(const int32_t* idx, int cnt, int
 #pragma unroll
     for (int b = 0; b < R; ++b) {
         const int j = b * kWave + lane;
-        v[b] = j < avail ? idx[base + j] : -1;
+        v[b] = j < avail ? to_global(idx)[base + j] : -1;
     }
     int nrows = 0;
 #pragma unroll
@@ -512,8 +520,8 @@ __device__ __forceinline__ void stage_step_rows(int nrows, int* s_row, float* s_
     for (int j = lane; j < nrows; j += kWave) {
         const int i = s_row[j];
         if (H.rsr_thr != 0 && rsr_sampled(rsr_s2, H.rsr_thr, i)) s_row[j] = (int)((uint32_t)i | 0x80000000u);
-        const int tn = t[i] + 1;
-        t[i] = tn;
+        const int tn = to_global(t)[i] + 1;
+        to_global(t)[i] = tn;
         const float ft = (float)tn;
         const float b1 = -expm1f(ft * H.logb1);
         const float b2 = -expm1f(ft * H.logb2);

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void step_view_kernel(KScene S, KHyper H, C
     __shared__ float s_rb1[kWavesPerBlock][UNIT];
     __shared__ float s_rsb2[kWavesPerBlock][UNIT];
     __shared__ float s_noise[kWavesPerBlock][NOISE ? 3 * UNIT : 1];   // position-noise displacements
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     const int lane = threadIdx.x % kWave;
     const int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * UNIT;
     if (w0 >= S.n) return;
