@@ -1578,9 +1578,7 @@ def main(argv=None) -> int:
         import synth
         scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
         cams = synth.camera_rig()
-        order = synth.camera_order(len(cams), 400, seed=0)
-        print(json.dumps(run_next_rows(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams, order)),
-              flush=True)
+        print(json.dumps(run_next_rows(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams)), flush=True)
         return 0
     if args.unfused_only:
         import torch
@@ -1588,8 +1586,7 @@ def main(argv=None) -> int:
         import synth
         scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
         cams = synth.camera_rig()
-        order = synth.camera_order(len(cams), 200, seed=0)
-        print(json.dumps(run_unfused(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams, order)), flush=True)
+        print(json.dumps(run_unfused(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams)), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the AdamW-GS step has no cross-GPU exchange to measure "

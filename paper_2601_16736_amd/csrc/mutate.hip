@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void prune_count_kernel(KMut M)
 __global__ __launch_bounds__(kBlock) void prune_move_kernel(KMut M, int64_t units)
 {
     __shared__ int s_row[kWavesPerBlock][kMutUnit];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     const int lane = threadIdx.x % kWave;
     const int64_t unit = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (unit >= units) return;
@@ -170,7 +170,7 @@ static_assert(kAppendUnit >= 1 && kAppendUnit <= 1024, "append unit");
 __global__ __launch_bounds__(kBlock) void append_kernel(KMut M, int64_t units)
 {
     __shared__ int s_row[kWavesPerBlock][kAppendUnit];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     const int lane = threadIdx.x % kWave;
     for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wave; u < units;
          u += (int64_t)gridDim.x * kWavesPerBlock) {

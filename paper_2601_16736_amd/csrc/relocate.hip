@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __res
         nl += __shfl_xor(nl, off);
         ne += __shfl_xor(ne, off);
     }
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     if (threadIdx.x % kWave == 0) {
         s_lt[wave] = nl;
         s_eq[wave] = ne;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void select_write_kernel(const float* __res
     const uint32_t K = st[4].prefix;
     const int rank = st[4].rank;
     if (rank <= 0) return;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     const int lane = threadIdx.x % kWave;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[J];

@@ -24,7 +24,7 @@ __device__ __forceinline__ void block_append(const bool (&vis)[kVisRounds], int6
 {
     __shared__ int s_cnt[kVisRounds * kWavesPerBlock];
     __shared__ int s_base;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // the same on every lane
     const int lane = threadIdx.x % kWave;
     uint64_t bal[kVisRounds];
 #pragma unroll

@@ -329,3 +329,22 @@ def test_a_failing_variant_does_not_suppress_the_line(monkeypatch, capsys):
     assert out["value"] > 0 and "roofline" in out
     assert "planted" in out["stream_ceiling"]["error"]
     assert any("planted" in json.dumps(v) for v in out["variants"])
+
+
+@pytest.mark.parametrize("flag", ["--next-only", "--unfused-only"])
+def test_single_leg_flags_print_their_leg(flag, monkeypatch, capsys):
+    import types
+
+    import torch
+    fake = _FakeGS(torch)
+    monkeypatch.setitem(sys.modules, "paper_2601_16736_amd", fake)
+    monkeypatch.setattr(bench, "DEVICE", "cpu")
+    monkeypatch.setattr(bench, "N_PRIMS", 3000)
+    monkeypatch.setattr(bench, "CHECK_UNFUSED", False)
+    monkeypatch.setattr(bench, "TimingEvents", _FakeEvents)
+    stream = types.SimpleNamespace(cuda_stream=0)
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
+    monkeypatch.setattr(torch.cuda, "current_stream", lambda *a: stream)
+    assert bench.main([flag]) == 0
+    line = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
+    assert len(line) == 1 and "error" not in json.loads(line[0])
