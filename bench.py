@@ -1292,18 +1292,26 @@ def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
             rp["alg_GBps"] = {k: out["algorithmic_bytes_per_step_bf16"] / (v * 1e-3) / 1e9
                               for k, v in rp["kernel_ms_per_step"].items()}
         out["rows_probe_bf16"] = rp
+        rp = guarded("batched rows probe, packed", batched_rows_ceiling, torch, scenes, n_masks, min(steps, 40),
+                     shapes=((128, 2), (128, 4), (64, 2), (64, 4), (32, 4), (128, 8)), packed=True)
+        if "error" not in rp:
+            rp["alg_GBps"] = {k: out["algorithmic_bytes_per_step_bf16"] / (v * 1e-3) / 1e9
+                              for k, v in rp["kernel_ms_per_step"].items()}
+        out["rows_probe_bf16_packed"] = rp
     scenes.clear()
     torch.cuda.empty_cache()
     return out
 
 
 def batched_rows_ceiling(torch, scenes, n_masks: int, steps: int,
-                         shapes=((32, 4), (64, 4), (128, 4), (32, 8), (64, 8), (128, 8))) -> dict:
+                         shapes=((32, 4), (64, 4), (128, 4), (32, 8), (64, 8), (128, 8)), packed: bool = False) -> dict:
     """The rows probe (the masked step's access pattern, no arithmetic; BF16
     moments) over each scene of the batch with its own masks, one launch per
     scene, each launch timed with HIP events; the sum over the scenes of a
     step is that step's kernel time.  Per launch shape (window, chunk items
-    in flight), the mean over `steps` steps."""
+    in flight), the mean over `steps` steps.  packed: each scene's state as
+    one [n][PACKED_WIDTH] array per role (the packed plan's rows, padding
+    included), instead of one array per group."""
     import ctypes
 
     import bench_probe
@@ -1312,7 +1320,7 @@ def batched_rows_ceiling(torch, scenes, n_masks: int, steps: int,
     lib = bench_probe.load()
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
-    dims = [d for _, d, _, _ in synth.GROUPS_59]
+    dims = [PACKED_WIDTH] if packed else [d for _, d, _, _ in synth.GROUPS_59]
     ng = len(dims)
     cd = (ctypes.c_int32 * ng)(*dims)
     res = {}
@@ -1320,8 +1328,14 @@ def batched_rows_ceiling(torch, scenes, n_masks: int, steps: int,
         total_ms = 0.0
         for sc in scenes:
             n = sc["n"]
-            arrs = [(p.clone(), g, torch.zeros(p.shape, dtype=torch.bfloat16, device=dev),
-                     torch.zeros(p.shape, dtype=torch.bfloat16, device=dev)) for p, g in zip(sc["params"], sc["grads"])]
+            if packed:
+                arrs = [(torch.randn((n, PACKED_WIDTH), device=dev), torch.randn((n, PACKED_WIDTH), device=dev) * 1e-3,
+                         torch.zeros((n, PACKED_WIDTH), dtype=torch.bfloat16, device=dev),
+                         torch.zeros((n, PACKED_WIDTH), dtype=torch.bfloat16, device=dev))]
+            else:
+                arrs = [(p.clone(), g, torch.zeros(p.shape, dtype=torch.bfloat16, device=dev),
+                         torch.zeros(p.shape, dtype=torch.bfloat16, device=dev))
+                        for p, g in zip(sc["params"], sc["grads"])]
             t = torch.zeros(n, dtype=torch.int32, device=dev)
             ptrs = [(ctypes.c_void_p * ng)(*[a[k].data_ptr() for a in arrs]) for k in range(4)]
             ev = TimingEvents(steps)
@@ -1345,7 +1359,8 @@ def batched_rows_ceiling(torch, scenes, n_masks: int, steps: int,
     best = min(res, key=res.get)
     return {"kernel_ms_per_step": res, "best_shape": best, "best_kernel_ms_per_step": res[best],
             "kind": "rows probe (masked-step access pattern, BF16 moments, no arithmetic) per scene with the "
-                    "scene's own masks; per step: sum of the scenes' kernel times"}
+                    "scene's own masks; per step: sum of the scenes' kernel times"
+                    + (f"; packed rows: one [n][{PACKED_WIDTH}] array per role" if packed else "")}
 
 
 def run_mcmc(gs, torch, cams, steps: int = 500, warmup: int = 10, path: str = "two_launch", counts_from=None):
