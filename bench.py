@@ -1175,6 +1175,60 @@ PACKED_WIDTH = 64
 PACKED_COLUMNS = {"sh": 0, "quats": 48, "means": 52, "scales": 55, "opacity": 58}
 
 
+def run_tuner(gs, torch, sd: SceneOnDevice, cams, steps: int = 20, z_fars=(17.5, 10.0)) -> dict:
+    """The schedule tuner on the 3M Morton scene with FP32 moments: gs_tune_mask
+    with the first camera's own visibility mask against gs_tune at that mask's
+    visible fraction (a synthetic i.i.d. mask), at the rig's far plane and at
+    a nearer one (fewer visible primitives).  Each choice's step is then timed
+    on that camera's mask: HIP events around `steps` launches, after 3 untimed
+    ones; the visibility and compaction run once beforehand.  Algorithmic
+    bytes: 1660 B per visible, plus 1 B of mask per primitive (masked) or 4 B
+    of index per visible (compacted)."""
+    import synth
+    dev = torch.device(DEVICE)
+    mask = torch.zeros(N_PRIMS, dtype=torch.uint8, device=dev)
+    idx = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    dims = [d for _, d, _, _ in synth.GROUPS_59]
+    groups = [gs.Group(p.clone(), sets[0], torch.zeros_like(p), torch.zeros_like(p), lr, dar_kind=dar,
+                       dar_lambda=LAMBDA_O if dar == 1 else (LAMBDA_S if dar == 2 else 0.0), dar_clip=CLIP)
+              for (name, dim, lr, dar), p, sets in zip(synth.GROUPS_59, sd.params, sd.grads)]
+    t = torch.zeros(N_PRIMS, dtype=torch.int32, device=dev)
+    names = {gs.GS_SCHED_COMPACTED: "compacted", gs.GS_SCHED_MASKED: "masked"}
+    out = {"workload": "3M-primitive scene, Morton order, FP32, one camera's mask", "cases": []}
+    c = cams[0]
+    for z_far in z_fars:
+        cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, z_far)
+        gs.gs_visibility(sd.params[0], cam, mask=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+        torch.cuda.synchronize()
+        vis = int(cnt.item())
+        gs.gs_tune_clear()
+        choices = {"own_mask": gs.gs_tune_mask(N_PRIMS, dims, mask),
+                   "iid_mask": gs.gs_tune(N_PRIMS, dims, max(vis, 1) / N_PRIMS)}
+        gs.gs_tune_clear()
+        case = {"z_far": z_far, "visible": vis}
+        for label, (sched, unit) in choices.items():
+            cfg = gs.StepConfig(reg_norm=REG_NORM, iteration=1, schedule=sched, unit=unit)
+            for _ in range(3):
+                gs.adamw_gs_step(groups, N_PRIMS, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+            ev = TimingEvents(1)
+            ev.record("start", 0, stream)
+            for _ in range(steps):
+                gs.adamw_gs_step(groups, N_PRIMS, t, cfg, visible=mask, vis_idx=idx, vis_count=cnt, stream=stream)
+            ev.record("end", 0, stream)
+            torch.cuda.synchronize()
+            us = ev.ms(0) * 1e3 / steps
+            ev.close()
+            alg = vis * BYTES_PER_VISIBLE["f32"] + (N_PRIMS if sched == gs.GS_SCHED_MASKED else 4 * vis)
+            case[label] = {"schedule": names.get(sched, str(sched)), "unit": unit, "step_kernel_us": us,
+                           "achieved_GBps": alg / us / 1e3}
+        out["cases"].append(case)
+    del groups, t
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(gs, torch, steps: int = 300, warmup: int = 10, n_masks: int = 8,
                 forms=("batched_bf16", "batched_bf16_packed", "batched_bf16_resident", "per_scene_bf16",
                        "per_scene_f32"), rows_probe: bool = True):
@@ -1507,6 +1561,8 @@ def main(argv=None) -> int:
                     help="with --sweep: only this scene size (at z_far 17.5), e.g. for a profiled run")
     ap.add_argument("--next-only", action="store_true",
                     help="only run the widened rows (noise, AIU, multi-view, prune/append) on the 3M Morton scene")
+    ap.add_argument("--tuner-only", action="store_true",
+                    help="only run the schedule tuner on the 3M Morton scene's own mask against an i.i.d. one")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 16-scene batched workload (for profiling)")
     ap.add_argument("--batched-steps", type=int, default=300,
@@ -1594,6 +1650,13 @@ def main(argv=None) -> int:
         scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
         cams = synth.camera_rig()
         print(json.dumps(run_next_rows(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), cams)), flush=True)
+        return 0
+    if args.tuner_only:
+        import torch
+        import paper_2601_16736_amd as gs
+        import synth
+        scene = synth.scene_uniform(N_PRIMS, seed=0, groups=synth.GROUPS_59)
+        print(json.dumps(run_tuner(gs, torch, SceneOnDevice(gs, torch, scene, "morton"), synth.camera_rig())), flush=True)
         return 0
     if args.unfused_only:
         import torch
@@ -1685,6 +1748,8 @@ def main(argv=None) -> int:
             if "error" not in unf:
                 unf["fused_speedup"] = unf["ms_per_step"] / fused_ms if fused_ms else None
             variants.append({"unfused_comparator": unf})
+            variants.append({"tuner_3m": guarded("tuner on the scene's own mask", run_tuner, gs, torch,
+                                                 layouts["morton"], cams)})
         del layouts
         torch.cuda.empty_cache()
         variants.append({"config1_100k": guarded("100k plain (cache-resident)", run_config1, gs, torch)})

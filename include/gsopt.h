@@ -418,6 +418,18 @@ gs_status gs_relocate_reset_noalloc(const float* key, int64_t key_stride, int64_
 gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, float visible_fraction,
                   int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit);
 
+/*
+ * As gs_tune, but the candidates are timed with the caller's own visibility
+ * mask (mask [n] uint8, device, read only; nonzero = visible) instead of an
+ * i.i.d. Bernoulli one.  In a spatially ordered scene the visible rows come
+ * in runs, which favours other schedules and units than isolated rows at
+ * the same fraction.  The winner is recorded for GS_SCHED_AUTO under the
+ * mask's own visible fraction.  GS_EINVAL for a NULL mask or one with no
+ * visible entry; otherwise as gs_tune (own buffers, synchronizes the device).
+ */
+gs_status gs_tune_mask(int64_t n, const int32_t* dims, int32_t n_groups, const uint8_t* mask,
+                       int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit);
+
 /* Removes every tuner entry. */
 void gs_tune_clear(void);
 

@@ -123,6 +123,8 @@ _lib.gs_relocate_reset_noalloc.argtypes = [_vp, _i64, _i64, _i64, ctypes.POINTER
 _lib.gs_tune.restype = _i32
 _lib.gs_tune.argtypes = [_i64, ctypes.POINTER(_i32), _i32, ctypes.c_float, _i32, ctypes.POINTER(_i32),
                          ctypes.POINTER(_i32)]
+_lib.gs_tune_mask.restype = _i32
+_lib.gs_tune_mask.argtypes = [_i64, ctypes.POINTER(_i32), _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 _lib.gs_tune_clear.restype = None
 _lib.gs_tune_clear.argtypes = []
 _lib.gs_spatial_order_workspace_size.restype = _sz
@@ -142,7 +144,7 @@ _lib.gs_append.argtypes = [ctypes.POINTER(gs_group), _i32, _i32, _i64, _vp, _i64
 EXPORTED = ["gs_last_error", "gs_version", "gs_reg_norm", "gs_visibility", "gs_visibility_multi", "gs_compact",
             "adamw_gs_step", "adamw_gs_step_view", "gs_batch_create", "adamw_gs_step_batched", "gs_batch_set_resident", "gs_batch_scene_schedule",
             "gs_batch_destroy",
-            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_relocate_reset_noalloc", "gs_tune", "gs_tune_clear",
+            "gs_relocate_workspace_size", "gs_relocate_reset", "gs_relocate_reset_noalloc", "gs_tune", "gs_tune_mask", "gs_tune_clear",
             "gs_spatial_order_workspace_size", "gs_spatial_order", "gs_gather_rows", "gs_prune_workspace_size",
             "gs_prune", "gs_append"]
 
@@ -492,6 +494,16 @@ def gs_tune(n: int, dims: Sequence[int], visible_fraction: float, moment_dtype: 
     s, u = ctypes.c_int32(0), ctypes.c_int32(0)
     _check(_lib.gs_tune(int(n), d, len(dims), float(visible_fraction), int(moment_dtype), ctypes.byref(s),
                         ctypes.byref(u)))
+    return int(s.value), int(u.value)
+
+
+def gs_tune_mask(n: int, dims: Sequence[int], mask, moment_dtype: int = GS_MOMENT_F32):
+    """Times the schedules with the caller's visibility mask (device uint8
+    tensor or address); returns (schedule, unit)."""
+    d = (ctypes.c_int32 * len(dims))(*[int(x) for x in dims])
+    s, u = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.gs_tune_mask(int(n), d, len(dims), _ptr(mask), int(moment_dtype), ctypes.byref(s),
+                             ctypes.byref(u)))
     return int(s.value), int(u.value)
 
 

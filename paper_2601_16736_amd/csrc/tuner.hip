@@ -2,6 +2,7 @@
 // unit sizes on synthetic buffers and keeps the fastest per bucket of
 // (primitive count, visible fraction, moment dtype).
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -76,19 +77,39 @@ extern "C" void gs_tune_clear(void)
     g_table.clear();
 }
 
-extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, float visible_fraction,
-                             int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit)
+namespace {
+
+// Argument checks shared by both tuner entry points.
+gs_status check_tune_args(const char* who, int64_t n, const int32_t* dims, int32_t n_groups, int32_t moment_dtype)
 {
-    clear_error();
-    if (n < 1 || n >= ((int64_t)1 << 31)) return set_error(GS_EINVAL, "gs_tune: n must be in [1, 2^31)");
-    if (dims == nullptr || n_groups < 1 || n_groups > GS_MAX_GROUPS)
-        return set_error(GS_EINVAL, "gs_tune: bad dims / n_groups");
-    if (!(visible_fraction > 0.0f && visible_fraction <= 1.0f))
-        return set_error(GS_EINVAL, "gs_tune: visible_fraction must be in (0, 1]");
-    if (moment_dtype != GS_MOMENT_F32 && moment_dtype != GS_MOMENT_BF16)
-        return set_error(GS_EINVAL, "gs_tune: unknown moment_dtype");
+    char msg[128];
+    if (n < 1 || n >= ((int64_t)1 << 31)) {
+        snprintf(msg, sizeof msg, "%s: n must be in [1, 2^31)", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (dims == nullptr || n_groups < 1 || n_groups > GS_MAX_GROUPS) {
+        snprintf(msg, sizeof msg, "%s: bad dims / n_groups", who);
+        return set_error(GS_EINVAL, msg);
+    }
+    if (moment_dtype != GS_MOMENT_F32 && moment_dtype != GS_MOMENT_BF16) {
+        snprintf(msg, sizeof msg, "%s: unknown moment_dtype", who);
+        return set_error(GS_EINVAL, msg);
+    }
     for (int g = 0; g < n_groups; ++g)
-        if (dims[g] < 1 || dims[g] > 4096) return set_error(GS_EINVAL, "gs_tune: dim out of range");
+        if (dims[g] < 1 || dims[g] > 4096) {
+            snprintf(msg, sizeof msg, "%s: dim out of range", who);
+            return set_error(GS_EINVAL, msg);
+        }
+    return GS_OK;
+}
+
+// Times every (schedule, unit) candidate on buffers of n zero rows and
+// records the fastest.  user_mask == nullptr: the visibility is a synthetic
+// Bernoulli(visible_fraction) mask; else it is that device mask (only read),
+// and the entry is recorded under its own visible fraction.
+gs_status tune(const char* who, int64_t n, const int32_t* dims, int32_t n_groups, float visible_fraction,
+               const uint8_t* user_mask, int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit)
+{
 
     const bool bf16 = moment_dtype == GS_MOMENT_BF16;
     const size_t msz = bf16 ? 2 : 4;
@@ -118,23 +139,42 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
     DevBuf& bm = bufs[(size_t)n_groups * 4 + 1];
     DevBuf& bi = bufs[(size_t)n_groups * 4 + 2];
     DevBuf& bc = bufs[(size_t)n_groups * 4 + 3];
-    if (hipMalloc(&bt.p, (size_t)n * 4) != hipSuccess || hipMalloc(&bm.p, (size_t)n) != hipSuccess ||
+    if (hipMalloc(&bt.p, (size_t)n * 4) != hipSuccess ||
+        (user_mask == nullptr && hipMalloc(&bm.p, (size_t)n) != hipSuccess) ||
         hipMalloc(&bi.p, (size_t)n * 4) != hipSuccess || hipMalloc(&bc.p, 256) != hipSuccess)
         return set_error(GS_ENOMEM, "gs_tune: hipMalloc failed");
     if (hipMemset(bt.p, 0, (size_t)n * 4) != hipSuccess) return set_error(GS_EHIP, "gs_tune: hipMemset failed");
 
     hipStream_t st;
     if (hipStreamCreate(&st) != hipSuccess) return set_error(GS_EHIP, "gs_tune: hipStreamCreate failed");
-    const uint64_t thr = visible_fraction >= 1.0f ? ((uint64_t)1 << 32)
-                                                  : (uint64_t)std::floor((double)visible_fraction * 4294967296.0);
-    hipLaunchKernelGGL(bernoulli_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       (uint8_t*)bm.p, n, thr);
-    hipError_t e = launch_compact((const uint8_t*)bm.p, n, (int32_t*)bi.p, (int32_t*)bc.p, st);
+    const uint8_t* mask = user_mask;
+    if (mask == nullptr) {
+        const uint64_t thr = visible_fraction >= 1.0f
+                                 ? ((uint64_t)1 << 32)
+                                 : (uint64_t)std::floor((double)visible_fraction * 4294967296.0);
+        hipLaunchKernelGGL(bernoulli_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (uint8_t*)bm.p, n, thr);
+        mask = (const uint8_t*)bm.p;
+    }
+    hipError_t e = launch_compact(mask, n, (int32_t*)bi.p, (int32_t*)bc.p, st);
+    if (user_mask != nullptr) {
+        // the mask's own visible fraction, for the record
+        int32_t count = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&count, bc.p, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && count <= 0) {
+            (void)hipStreamDestroy(st);
+            char msg[96];
+            snprintf(msg, sizeof msg, "%s: the mask has no visible entry", who);
+            return set_error(GS_EINVAL, msg);
+        }
+        visible_fraction = (float)((double)count / (double)n);
+    }
 
     s.n_groups = n_groups;
     s.bf16 = bf16 ? 1 : 0;
     s.n = n;
-    s.mask = (const uint8_t*)bm.p;
+    s.mask = mask;
     s.idx = (const int32_t*)bi.p;
     s.count = (const int32_t*)bc.p;
     s.t = (int32_t*)bt.p;
@@ -185,4 +225,27 @@ extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, f
     if (best_schedule) *best_schedule = best.sched;
     if (best_unit) *best_unit = best.unit;
     return GS_OK;
+}
+
+}  // namespace
+
+extern "C" gs_status gs_tune(int64_t n, const int32_t* dims, int32_t n_groups, float visible_fraction,
+                             int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit)
+{
+    clear_error();
+    const gs_status st = check_tune_args("gs_tune", n, dims, n_groups, moment_dtype);
+    if (st != GS_OK) return st;
+    if (!(visible_fraction > 0.0f && visible_fraction <= 1.0f))
+        return set_error(GS_EINVAL, "gs_tune: visible_fraction must be in (0, 1]");
+    return tune("gs_tune", n, dims, n_groups, visible_fraction, nullptr, moment_dtype, best_schedule, best_unit);
+}
+
+extern "C" gs_status gs_tune_mask(int64_t n, const int32_t* dims, int32_t n_groups, const uint8_t* mask,
+                                  int32_t moment_dtype, int32_t* best_schedule, int32_t* best_unit)
+{
+    clear_error();
+    const gs_status st = check_tune_args("gs_tune_mask", n, dims, n_groups, moment_dtype);
+    if (st != GS_OK) return st;
+    if (mask == nullptr) return set_error(GS_EINVAL, "gs_tune_mask: mask is NULL");
+    return tune("gs_tune_mask", n, dims, n_groups, 0.0f, mask, moment_dtype, best_schedule, best_unit);
 }

@@ -148,6 +148,11 @@ def test_tune_rejects_bad_arguments():
     for args in ((0, [3], 0.3), (100, [], 0.3), (100, [3], 0.0), (100, [3], 1.5), (100, [0], 0.3)):
         with pytest.raises(gs.GsError):
             gs.gs_tune(*args)
+    for args in ((0, [3], FAKE), (100, [], FAKE), (100, [0], FAKE), (100, [3], None)):
+        with pytest.raises(gs.GsError):
+            gs.gs_tune_mask(*args)
+    with pytest.raises(gs.GsError):
+        gs.gs_tune_mask(100, [3], FAKE, moment_dtype=7)
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -230,8 +230,15 @@ class _FakeGS:
     def gs_relocate_reset(self, key, k, groups, mom, t, reset_t, ws, stream=None):
         self._count("relocate")
 
-    def gs_tune(self, n, dims, p, mom):
+    def gs_tune(self, n, dims, p, mom=0):
         return (self.GS_SCHED_COMPACTED if p < 0.1 else self.GS_SCHED_MASKED), 64
+
+    def gs_tune_mask(self, n, dims, mask, mom=0):
+        self._count("tune_mask")
+        return self.GS_SCHED_MASKED, 32
+
+    def gs_tune_clear(self):
+        pass
 
 
 class _FakeEvents:
@@ -297,7 +304,7 @@ def test_default_run_under_the_driver_flags_prints_its_line(monkeypatch, capsys)
     names = set()
     for v in out["variants"]:
         names.update(v.keys())
-    assert {"next_rows", "unfused_comparator", "config1_100k", "batched", "mcmc_6m"} <= names
+    assert {"next_rows", "unfused_comparator", "tuner_3m", "config1_100k", "batched", "mcmc_6m"} <= names
     assert {"rows_f32", "rows_bf16"} <= set(out["stream_ceiling"])
     assert "two_launch_step_frac_of_best" in out["stream_ceiling"]["rows_f32"]
     assert fake.calls["step_view"] > 200 and fake.calls["relocate"] > 0 and fake.calls["batched"] > 0
@@ -316,7 +323,8 @@ def test_a_failing_variant_does_not_suppress_the_line(monkeypatch, capsys):
     def boom(*a, **k):
         raise IndexError("planted")
 
-    for leg in ("run_next_rows", "run_unfused", "run_config1", "run_batched", "run_mcmc_both", "stream_ceilings"):
+    for leg in ("run_next_rows", "run_unfused", "run_tuner", "run_config1", "run_batched", "run_mcmc_both",
+                "stream_ceilings"):
         monkeypatch.setattr(bench, leg, boom)
     stream = types.SimpleNamespace(cuda_stream=0)
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
@@ -331,7 +339,7 @@ def test_a_failing_variant_does_not_suppress_the_line(monkeypatch, capsys):
     assert any("planted" in json.dumps(v) for v in out["variants"])
 
 
-@pytest.mark.parametrize("flag", ["--next-only", "--unfused-only"])
+@pytest.mark.parametrize("flag", ["--next-only", "--unfused-only", "--tuner-only"])
 def test_single_leg_flags_print_their_leg(flag, monkeypatch, capsys):
     import types
 

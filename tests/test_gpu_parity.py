@@ -313,6 +313,38 @@ def test_auto_schedule_and_tuner():
     gs.gs_tune_clear()
 
 
+def test_tuner_on_the_scenes_own_mask():
+    """gs_tune_mask times the candidates with a given mask: runs of visible
+    rows (a spatially ordered scene) and isolated ones at about the same
+    fraction each give a valid choice, recorded under the mask's own
+    fraction, and the AUTO step that follows it matches the oracle."""
+    n = 50_000
+    dims = [d for _, d, _, _ in synth.GROUPS_59]
+    runs = ((np.arange(n) // 256) % 3 == 0).astype(np.uint8)          # runs of 256, a third visible
+    iid = synth.bernoulli_mask(n, float(runs.mean()), 8, 2)
+    for mask in (runs, iid):
+        gs.gs_tune_clear()
+        d_mask = torch.from_numpy(mask).to(DEV)
+        s, u = gs.gs_tune_mask(n, dims, d_mask)
+        assert s in (gs.GS_SCHED_COMPACTED, gs.GS_SCHED_MASKED) and u in (32, 64, 128, 256, 512)
+        st = make_state(gs, n, synth.GROUPS_59, 8)
+        set_grads(st, mask, 8, 1)
+        idx = torch.zeros(n, dtype=torch.int32, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+        gs.gs_compact(d_mask, idx, cnt)
+        cfg = gs.StepConfig(iteration=1, schedule=gs.GS_SCHED_AUTO, visible_hint=float(mask.mean()))
+        before = st.host()
+        gs.adamw_gs_step(st.groups, n, st.t, cfg, visible=d_mask, vis_idx=idx, vis_count=cnt)
+        torch.cuda.synchronize()
+        og = oracle_groups(before, synth.GROUPS_59, st.groups)
+        t_ref = before["_t"].copy()
+        oracle.adamw_gs_step(og, n, mask, t_ref, oracle_config(cfg))
+        compare(st.host(), before, og, synth.GROUPS_59, t_ref, mask.astype(bool), False, "auto-mask")
+    with pytest.raises(gs.GsError, match="no visible entry"):
+        gs.gs_tune_mask(n, dims, torch.zeros(n, dtype=torch.uint8, device=DEV))
+    gs.gs_tune_clear()
+
+
 # ---------------------------------------------------------------- trajectories
 def test_config1_trajectory_20_steps():
     """100k primitives, 59 floats each, Bernoulli(0.3) visibility and N(0,1e-3)
