@@ -132,6 +132,31 @@ __device__ __forceinline__ void load_keys(const float* __restrict__ key, int64_t
         o[j] = key_ord(key[ks * min(first + (int64_t)j * kBlock + threadIdx.x, n - 1)]);
 }
 
+// The block's keys for passes that only count them (digit histograms, the
+// counts below and equal to K), in no particular thread order: with unit
+// stride, a 16-byte aligned array and the whole block inside [0, n), four
+// 16-byte loads per thread instead of sixteen 4-byte ones.  Returns whether
+// that form was taken; then every loaded key is in range, else load_keys'
+// mapping and its index test apply.
+__device__ __forceinline__ bool load_keys_counted(const float* __restrict__ key, int64_t ks, int64_t n,
+                                                  int64_t first, uint32_t (&o)[kRelPerThread])
+{
+    if (ks == 1 && ((uintptr_t)key & 15u) == 0 && first + kRelPerBlock <= n) {
+        const float4* k4 = reinterpret_cast<const float4*>(key + first);
+#pragma unroll
+        for (int q = 0; q < kRelPerThread / 4; ++q) {
+            const float4 f = k4[q * kBlock + threadIdx.x];
+            o[4 * q + 0] = key_ord(f.x);
+            o[4 * q + 1] = key_ord(f.y);
+            o[4 * q + 2] = key_ord(f.z);
+            o[4 * q + 3] = key_ord(f.w);
+        }
+        return true;
+    }
+    load_keys(key, ks, n, first, o);
+    return false;
+}
+
 // Digit pass p (bits 31-8p .. 24-8p): histogram of the keys that match the
 // state narrowed by passes 0 .. p-1.
 __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
@@ -143,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     for (int w = 0; w < kWavesPerBlock; ++w) s_hist[w][threadIdx.x] = 0u;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[kRelPerThread];
-    load_keys(key, ks, n, first, o);
+    const bool whole = load_keys_counted(key, ks, n, first, o);
     const int shift = 24 - 8 * pass;
     const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist, pass - 1, shift + 8);
     if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
@@ -151,8 +176,8 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     uint32_t* mine = s_hist[threadIdx.x / kWave];
 #pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
-        const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
-        if (i < n && (o[j] & cur.mask) == cur.prefix) atomicAdd(&mine[(o[j] >> shift) & 0xFFu], 1u);
+        const bool in = whole || first + (int64_t)j * kBlock + threadIdx.x < n;
+        if (in && (o[j] & cur.mask) == cur.prefix) atomicAdd(&mine[(o[j] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
@@ -173,12 +198,12 @@ __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __res
     const bool any = fin.rank > 0;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[kRelPerThread];
-    load_keys(key, ks, n, first, o);
+    const bool whole = load_keys_counted(key, ks, n, first, o);
     int nl = 0, ne = 0;
 #pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
-        const int64_t i = first + (int64_t)j * kBlock + threadIdx.x;
-        if (i < n && any) {
+        const bool in = whole || first + (int64_t)j * kBlock + threadIdx.x < n;
+        if (in && any) {
             nl += o[j] < K;
             ne += o[j] == K;
         }

@@ -111,3 +111,30 @@ def test_select_past_the_inline_scan_limit():
         torch.cuda.synchronize()
         ref = np.sort(np.argsort(key, kind="stable")[:k])
         np.testing.assert_array_equal(sel.cpu().numpy().astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("layout", ["offset", "strided"])
+def test_select_unaligned_and_strided_keys(layout):
+    """Keys one float past a 16-byte boundary, or every third float of a
+    packed [n][3] tensor: the counting passes read them with per-key loads
+    instead of 16-byte ones, over whole blocks and a ragged last block."""
+    n = 3 * 4096 + 777
+    key = synth.rng(66).integers(-50, 50, n).astype(np.float32) * np.float32(0.125)
+    if layout == "offset":
+        base = torch.zeros(n + 1, dtype=torch.float32, device=DEV)
+        base[1:] = torch.from_numpy(key).to(DEV)
+        d_key = base[1:]
+        assert d_key.data_ptr() % 16 == 4
+    else:
+        base = torch.zeros((n, 3), dtype=torch.float32, device=DEV)
+        base[:, 1] = torch.from_numpy(key).to(DEV)
+        d_key = base[:, 1]
+        assert d_key.stride() == (3,)
+    st = make_state(gs, n, [("opacity", 1, 5e-2, 1), ("scale", 3, 5e-3, 2)], 7)
+    ws = torch.empty(gs.gs_relocate_workspace_size(n), dtype=torch.uint8, device=DEV)
+    for k in (1, 4096, 9000):
+        sel = torch.full((k,), -7, dtype=torch.int32, device=DEV)
+        print(f"relocate {layout} n={n} k={k}", flush=True)
+        gs.gs_relocate_reset(d_key, k, st.groups, 0, st.t, True, ws, selected=sel)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(sel.cpu().numpy().astype(np.int64), oracle.select_smallest(key, k))
