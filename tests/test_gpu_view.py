@@ -235,3 +235,37 @@ def test_view_step_rejects_bad_unit_and_camera():
         gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, [cam] * 33)
     with pytest.raises(gs.GsError):
         gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(), st.groups[0].param, [])
+
+
+@pytest.mark.parametrize("n,unit,bf16,noise", [(20_011, 0, False, False), (20_011, 0, True, False),
+                                               (100_003, 0, False, True), (1025, 32, True, True), (1, 0, False, False)])
+def test_view_step_aiu_with_and_without_mask_out(n, unit, bf16, noise):
+    """AIU without Re-State at the default windows, with and without
+    visible_out: both equal the two-launch path bit for bit, over three
+    steps (AIU rows need t > 0, so later steps sample more of them)."""
+    st = _scene(n, 60 + n % 89, bf16)
+    a_groups, a_t = _clone(st)
+    ref_groups, ref_t = _clone(st)
+    rig = synth.camera_rig()
+    for it in range(3):
+        c = rig[(n * 3 + 41 * it) % 200]
+        cam = gs.Camera(c.view, c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.z_near, c.z_far)
+        kw = dict(iteration=20 + it, seed=n, moment_dtype=int(bf16), stochastic_round=bf16, aiu_enable=True,
+                  aiu_ratio=0.3, aiu_scale=0.7, noise_enable=noise, noise_lr=0.02 / 1.6e-4, noise_t=0.5, unit=unit)
+        print(f"view aiu n={n} unit={unit} bf16={bf16} noise={noise} step={it}", flush=True)
+        mask_ref = torch.zeros(n, dtype=torch.uint8, device=DEV)
+        gs.gs_visibility(ref_groups[0].param, cam, mask=mask_ref)
+        gs.adamw_gs_step(ref_groups, n, ref_t, gs.StepConfig(schedule=gs.GS_SCHED_MASKED, **dict(kw, unit=128)),
+                         visible=mask_ref)
+        mask = torch.full((n,), 9, dtype=torch.uint8, device=DEV)
+        gs.adamw_gs_step_view(st.groups, n, st.t, gs.StepConfig(**kw), st.groups[0].param, cam, visible_out=mask)
+        gs.adamw_gs_step_view(a_groups, n, a_t, gs.StepConfig(**kw), a_groups[0].param, cam)
+        torch.cuda.synchronize()
+        assert torch.equal(mask, mask_ref)
+        for t in (st.t, a_t):
+            assert torch.equal(t, ref_t)
+        for x, y, r in zip(st.groups, a_groups, ref_groups):
+            for field in ("param", "exp_avg", "exp_avg_sq"):
+                assert torch.equal(_bits(getattr(x, field)), _bits(getattr(r, field)))
+                assert torch.equal(_bits(getattr(y, field)), _bits(getattr(r, field)))
+    assert int((ref_t > 0).sum()) > 0 or n == 1
