@@ -31,6 +31,11 @@ constexpr size_t kAlign = 256;
 constexpr int kHistCopies = 8;
 constexpr int kHistStride = 1024;
 constexpr int kHistWords = 4 * kHistCopies * kHistStride;
+// LDS digit histograms of a pass block: one per kSubLanes lanes, kSubStride
+// words apart (8 banks further on per copy)
+constexpr int kSubLanes = 16;
+constexpr int kSubHist = kBlock / kSubLanes;
+constexpr int kSubStride = 264;
 
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -162,10 +167,12 @@ __device__ __forceinline__ bool load_keys_counted(const float* __restrict__ key,
 __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
                                                              SelectState* st, int pass, uint32_t* hist)
 {
-    // one private histogram per wave: keys such as opacity logits fall into
-    // a few top digits, and four copies cut the LDS atomic collisions fourfold
-    __shared__ uint32_t s_hist[kWavesPerBlock][256];
-    for (int w = 0; w < kWavesPerBlock; ++w) s_hist[w][threadIdx.x] = 0u;
+    // one private histogram per quarter-wave: keys such as opacity logits
+    // fall into a few adjacent top digits, and at most 16 lanes of an LDS
+    // atomic then meet on one word; copies kSubStride words apart put the
+    // four quarters' copies of neighbouring digits in different banks
+    __shared__ uint32_t s_hist[kSubHist * kSubStride];
+    for (int i = threadIdx.x; i < kSubHist * kSubStride; i += kBlock) s_hist[i] = 0u;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
     uint32_t o[kRelPerThread];
     const bool whole = load_keys_counted(key, ks, n, first, o);
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist, pass - 1, shift + 8);
     if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
     __syncthreads();
-    uint32_t* mine = s_hist[threadIdx.x / kWave];
+    uint32_t* mine = s_hist + (threadIdx.x / kSubLanes) * kSubStride;
 #pragma unroll
     for (int j = 0; j < kRelPerThread; ++j) {
         const bool in = whole || first + (int64_t)j * kBlock + threadIdx.x < n;
@@ -181,7 +188,8 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     }
     __syncthreads();
     uint32_t c = 0;
-    for (int w = 0; w < kWavesPerBlock; ++w) c += s_hist[w][threadIdx.x];
+#pragma unroll
+    for (int h = 0; h < kSubHist; ++h) c += s_hist[h * kSubStride + threadIdx.x];
     if (c) atomicAdd(&pass_hist(hist, pass, blockIdx.x % kHistCopies)[threadIdx.x], c);
 }
 
