@@ -387,7 +387,7 @@ gs_status gs_relocate_reset(const float* key, int64_t key_stride, int64_t n, int
  * serving loops, harnesses that forbid allocation): gs_relocate_reset with
  * no workspace argument.  Same selection, results and argument rules; the
  * workspace is instead a device array of fixed size inside the library
- * (about 390 KB, one copy on each device the library runs on, held until the
+ * (about 640 KB, one copy on each device the library runs on, held until the
  * process ends), so n is limited to GS_RELOCATE_NOALLOC_MAX_N (GS_EINVAL
  * above it; gs_relocate_reset serves larger n).  The call allocates nothing:
  * its first call on a device looks up that device's copy (with the device

@@ -3,9 +3,11 @@
 // optimizer-side half of relocating dead primitives.
 //
 // Selection is a most-significant-digit radix select over the keys mapped to
-// order-preserving uint32: four 8-bit passes narrow the key of the k-th
-// smallest element (K) and the number r of elements equal to K that still
-// belong to the selection.  Per-block counts of keys < K and == K, summed
+// order-preserving uint32: three passes over the keys narrow the key of the
+// k-th smallest element (K) and the number r of elements equal to K that
+// still belong to the selection, two 8-bit digits and then the last 16 bits
+// at once (a 256-bin histogram of the third digit and a 65536-bin table of
+// the last two, which only keys matching the 16-bit prefix reach).  Per-block counts of keys < K and == K, summed
 // over the blocks before each block, let every block pick its keys < K and
 // the first r keys == K in index order, writing the selected indices in
 // ascending order and zeroing their state rows.
@@ -37,13 +39,18 @@ constexpr int kSubLanes = 16;
 constexpr int kSubHist = kBlock / kSubLanes;
 constexpr int kSubStride = 264;
 
+// The last pass's table of the last two digits: bin (d2 << 8) | d3.
+constexpr int kFineWords = 1 << 16;
+constexpr int kLastPass = 2;
+
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout for n keys: the select states (one aligned slot), the
-// pass histograms, then the per-block counts below K and equal to K.
+// pass histograms, the last pass's 16-bit table, then the per-block counts
+// below K and equal to K.
 constexpr size_t workspace_bytes_for(int64_t n)
 {
-    return kAlign + align_up((size_t)kHistWords * 4) +
+    return kAlign + align_up((size_t)kHistWords * 4) + align_up((size_t)kFineWords * 4) +
            2 * align_up((size_t)((n + kRelPerBlock - 1) / kRelPerBlock) * 4);
 }
 
@@ -66,7 +73,8 @@ struct SelectState {
     int32_t rank;      // elements still to take among those matching prefix
     int32_t pad;
 };
-// st[p]: the state digit pass p starts from (p = 0..3); st[4]: the final one.
+// st[p]: the state digit pass p starts from (p = 0..2); st[3]: after the
+// third digit; st[4]: the final one.
 static_assert(5 * sizeof(SelectState) <= kAlign, "states fit the first aligned slot");
 
 // -0.0 and +0.0 compare equal, so both map to the key of +0.0
@@ -76,9 +84,11 @@ __device__ __forceinline__ uint32_t key_ord(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// st[0] = the initial state; every copy of the four pass histograms
-// cleared.  One block of 256 threads per (pass, copy).
-__global__ void select_init_kernel(SelectState* st, uint32_t* hist, int32_t k)
+// st[0] = the initial state; every copy of the pass histograms and the
+// 16-bit table cleared.  One block of 256 threads per (pass, copy), then one
+// per 256 words of the table.
+constexpr int kInitBlocks = 4 * kHistCopies + kFineWords / 256;
+__global__ void select_init_kernel(SelectState* st, uint32_t* hist, uint32_t* fine, int32_t k)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st[0].prefix = 0u;
@@ -86,7 +96,8 @@ __global__ void select_init_kernel(SelectState* st, uint32_t* hist, int32_t k)
         st[0].rank = k;
         st[0].pad = 0;
     }
-    hist[blockIdx.x * kHistStride + threadIdx.x] = 0u;
+    if (blockIdx.x < 4 * kHistCopies) hist[blockIdx.x * kHistStride + threadIdx.x] = 0u;
+    else fine[(blockIdx.x - 4 * kHistCopies) * 256 + threadIdx.x] = 0u;
 }
 
 __device__ __forceinline__ uint32_t* pass_hist(uint32_t* hist, int pass, int copy)
@@ -94,18 +105,18 @@ __device__ __forceinline__ uint32_t* pass_hist(uint32_t* hist, int pass, int cop
     return hist + (pass * kHistCopies + copy) * kHistStride;
 }
 
-// The state after a digit pass, from the state before it and the pass's
-// histogram copies: the bucket where the running count first reaches `rank`
-// fixes the digit.  Every block of the next kernel computes it (8 KB read
-// from L2 and a 256-wide scan), so no kernel waits on another block; block 0
-// records it.  Needs all 256 threads of the block.
-__device__ SelectState narrow(const SelectState* prev, uint32_t* hist, int pass, int shift)
+// The state after a digit, from the state before it and the digit's 256
+// counts (summed over `copies` arrays kHistStride words apart): the bucket
+// where the running count first reaches `rank` fixes the digit.  Every block
+// of the next kernel computes it (up to 8 KB read from L2 and a 256-wide
+// scan), so no kernel waits on another block; block 0 records it.  Needs all
+// 256 threads of the block; two calls in a row need a barrier between them.
+__device__ SelectState narrow(const SelectState* prev, const uint32_t* counts, int copies, int shift)
 {
     __shared__ uint32_t s_inc[256];
     __shared__ SelectState s_st;
     uint32_t c = 0;
-#pragma unroll
-    for (int cp = 0; cp < kHistCopies; ++cp) c += pass_hist(hist, pass, cp)[threadIdx.x];
+    for (int cp = 0; cp < copies; ++cp) c += counts[cp * kHistStride + threadIdx.x];
     s_inc[threadIdx.x] = c;
     if (threadIdx.x == 0) s_st = *prev;
     __syncthreads();
@@ -164,8 +175,10 @@ __device__ __forceinline__ bool load_keys_counted(const float* __restrict__ key,
 
 // Digit pass p (bits 31-8p .. 24-8p): histogram of the keys that match the
 // state narrowed by passes 0 .. p-1.
+// The last pass (kLastPass) also adds every matching key to the 16-bit table.
 __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
-                                                             SelectState* st, int pass, uint32_t* hist)
+                                                             SelectState* st, int pass, uint32_t* hist,
+                                                             uint32_t* fine)
 {
     // one private histogram per quarter-wave: keys such as opacity logits
     // fall into a few adjacent top digits, and at most 16 lanes of an LDS
@@ -177,7 +190,8 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     uint32_t o[kRelPerThread];
     const bool whole = load_keys_counted(key, ks, n, first, o);
     const int shift = 24 - 8 * pass;
-    const SelectState cur = pass == 0 ? st[0] : narrow(&st[pass - 1], hist, pass - 1, shift + 8);
+    const SelectState cur =
+        pass == 0 ? st[0] : narrow(&st[pass - 1], pass_hist(hist, pass - 1, 0), kHistCopies, shift + 8);
     if (pass > 0 && blockIdx.x == 0 && threadIdx.x == 0) st[pass] = cur;
     __syncthreads();
     uint32_t* mine = s_hist + (threadIdx.x / kSubLanes) * kSubStride;
@@ -185,6 +199,27 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
     for (int j = 0; j < kRelPerThread; ++j) {
         const bool in = whole || first + (int64_t)j * kBlock + threadIdx.x < n;
         if (in && (o[j] & cur.mask) == cur.prefix) atomicAdd(&mine[(o[j] >> shift) & 0xFFu], 1u);
+    }
+    if (pass == kLastPass) {
+        // Few keys match a 16-bit prefix, but ties can make many: the wave
+        // adds each distinct bin once, with the number of its lanes in it.
+        const int lane = threadIdx.x % kWave;
+#pragma unroll
+        for (int j = 0; j < kRelPerThread; ++j) {
+            const bool in = whole || first + (int64_t)j * kBlock + threadIdx.x < n;
+            bool want = in && (o[j] & cur.mask) == cur.prefix;
+            const int bin = (int)(o[j] & 0xFFFFu);
+            uint64_t pend = __ballot(want);
+            while (pend != 0) {
+                const int src = __builtin_ctzll(pend);
+                const int lb = __builtin_amdgcn_readlane(bin, src);
+                const bool same = want && bin == lb;
+                const uint64_t grp = __ballot(same);
+                if (lane == src) atomicAdd(&fine[lb], (uint32_t)__popcll(grp));
+                want = want && !same;
+                pend &= ~grp;
+            }
+        }
     }
     __syncthreads();
     uint32_t c = 0;
@@ -194,14 +229,21 @@ __global__ __launch_bounds__(kBlock) void select_hist_kernel(const float* __rest
 }
 
 // Per block: keys below K and keys equal to K, K being the key of the k-th
-// smallest (the state after the last pass, recorded in st[4] by block 0).
+// smallest: the third digit from the last pass's histogram copies, then the
+// fourth from that digit's row of the 16-bit table (states recorded in st[3]
+// and st[4] by block 0).
 __global__ __launch_bounds__(kBlock) void select_count_kernel(const float* __restrict__ key, int64_t ks, int64_t n,
-                                                              SelectState* st, uint32_t* hist, int32_t* lt,
-                                                              int32_t* eq)
+                                                              SelectState* st, uint32_t* hist,
+                                                              const uint32_t* fine, int32_t* lt, int32_t* eq)
 {
     __shared__ int s_lt[kWavesPerBlock], s_eq[kWavesPerBlock];
-    const SelectState fin = narrow(&st[3], hist, 3, 0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st[4] = fin;
+    const SelectState s3 = narrow(&st[kLastPass], pass_hist(hist, kLastPass, 0), kHistCopies, 8);
+    __syncthreads();   // narrow's shared state is taken again below
+    const SelectState fin = narrow(&s3, fine + ((s3.prefix >> 8) & 0xFFu) * 256, 1, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[3] = s3;
+        st[4] = fin;
+    }
     const uint32_t K = fin.prefix;
     const bool any = fin.rank > 0;
     const int64_t first = (int64_t)blockIdx.x * kRelPerBlock;
@@ -477,13 +519,17 @@ hipError_t launch_relocate(const float* key, int64_t ks, int64_t n, int64_t k, c
     char* p = static_cast<char*>(ws);
     SelectState* st = reinterpret_cast<SelectState*>(p);
     uint32_t* hist = reinterpret_cast<uint32_t*>(p + kAlign);
-    int32_t* lt = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes);
-    int32_t* eq = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + align_up((size_t)nblocks * 4));
+    const size_t fine_bytes = align_up((size_t)kFineWords * 4);
+    uint32_t* fine = reinterpret_cast<uint32_t*>(p + kAlign + hist_bytes);
+    int32_t* lt = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + fine_bytes);
+    int32_t* eq = reinterpret_cast<int32_t*>(p + kAlign + hist_bytes + fine_bytes + align_up((size_t)nblocks * 4));
 
-    hipLaunchKernelGGL(select_init_kernel, dim3(4 * kHistCopies), dim3(256), 0, stream, st, hist, (int32_t)k);
-    for (int pass = 0; pass < 4; ++pass)
-        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, pass, hist);
-    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, hist, lt, eq);
+    hipLaunchKernelGGL(select_init_kernel, dim3(kInitBlocks), dim3(256), 0, stream, st, hist, fine, (int32_t)k);
+    for (int pass = 0; pass <= kLastPass; ++pass)
+        hipLaunchKernelGGL(select_hist_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, pass, hist,
+                           fine);
+    hipLaunchKernelGGL(select_count_kernel, dim3(nblocks), dim3(kBlock), 0, stream, key, ks, n, st, hist, fine, lt,
+                       eq);
     if (nblocks <= kInlineScanBlocks) {
         launch_write<true>(nblocks, stream, key, ks, n, st, lt, eq, selected, s, reset_t);
     } else {
