@@ -138,3 +138,17 @@ def test_select_unaligned_and_strided_keys(layout):
         gs.gs_relocate_reset(d_key, k, st.groups, 0, st.t, True, ws, selected=sel)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(sel.cpu().numpy().astype(np.int64), oracle.select_smallest(key, k))
+
+
+def test_select_keys_sharing_the_16_bit_prefix():
+    """Every key has the same upper 16 bits (1.0 plus up to 65535 ulps), so all
+    of them reach the last pass's 16-bit table, a wave's lanes in up to 64
+    different bins; shuffled, with repeats (ties) and a ragged last block."""
+    n = 3 * 4096 + 5
+    r = synth.rng(67)
+    low = r.integers(0, 1 << 16, n).astype(np.uint32)
+    low[::5] = low[0]                                   # a large run of equal keys
+    key = (np.uint32(0x3F800000) | low).view(np.float32)
+    assert len({int(x) >> 16 for x in key.view(np.uint32)}) == 1
+    for k in (1, 777, n // 5, n // 2, n - 1):
+        _run(key, k, seed=k, spec=[("opacity", 1, 5e-2, 1)])
